@@ -1,0 +1,332 @@
+"""Synthetic physics tables and their binary blob.
+
+The paper loads its cross sections per interaction, material and energy from
+data files before any transport starts (Sec. 2.2) and keeps them read-only on
+the device (Sec. 2.3).  Those files (DPM's PENELOPE-derived data) are not
+available, so this module writes a stand-in: closed-form textbook models for
+the processes DPM simulates (Sec. 2.1), tabulated in FP64 on one shared
+logarithmic energy grid.  The tables are *input data* to the transport, in the
+same role as the paper's files; the transport itself (interpolation, majorant,
+range inversion, sampling) is implemented separately by each consumer.
+
+Quantities per material, per gram (the order is the blob's quantity index):
+
+  0  mu_C/rho     Klein-Nishina Compton attenuation            cm^2/g
+  1  mu_pe/rho    photoelectric, Z^4/E^3 model                 cm^2/g
+  2  mu_pp/rho    pair production above 2 m c^2                cm^2/g
+  3  R            restricted CSDA range                        g/cm^2
+  4  1/(lambda1 rho)  elastic transport cross section          cm^2/g
+  5  Sigma_M/rho  hard Moller cross section (W > W_cc)         cm^2/g
+  6  Sigma_B/rho  hard bremsstrahlung cross section (W > W_cr) cm^2/g
+  7  L_r/rho      restricted total stopping power              MeV cm^2/g
+
+Absorption energies are 200 keV (electrons) and 50 keV (photons) (Sec. 3);
+the production thresholds W_cc and W_cr are taken equal to them.
+"""
+from __future__ import annotations
+
+import math
+import struct
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy import integrate, optimize
+
+# CODATA 2018
+MC2 = 0.51099895                # electron rest energy, MeV
+R_E = 2.8179403262e-13          # classical electron radius, cm
+N_A = 6.02214076e23             # 1/mol
+ALPHA = 1.0 / 137.035999084
+HBARC = 1.973269804e-11         # MeV cm
+A0 = 5.29177210903e-9           # Bohr radius, cm
+MEV_PER_G_TO_GY = 1.602176634e-10
+
+# Model constants of the synthetic processes.
+C_PE = 1.213e-8                 # cm^2 MeV^3 / g, photoelectric
+C_PP = 8.722e-4                 # cm^2 / g, pair
+K_B = 5.07e-3                   # cm^2 / g, bremsstrahlung
+
+N_E = 512
+E_MIN = 1.0e-3                  # MeV
+E_MAX = 20.0                    # MeV
+N_Q = 8
+
+Q_MU_C, Q_MU_PE, Q_MU_PP, Q_RANGE, Q_LAMBDA1_INV, Q_SIGMA_M, Q_SIGMA_B, Q_L_R = range(8)
+QUANTITY_NAMES = ("mu_C", "mu_pe", "mu_pp", "R", "lambda1_inv", "Sigma_M", "Sigma_B", "L_r")
+
+BLOB_MAGIC = b"MCDTAB\x00\x01"
+BLOB_VERSION = 1
+FLAG_NO_HARD = 1                 # test variant: Sigma_M = Sigma_B = 0, unrestricted losses
+FLAG_PE_ONLY = 2                 # test variant: photons interact only by photoabsorption
+
+E_ABS_E = 0.2                   # MeV
+E_ABS_G = 0.05                  # MeV
+KAPPA_STEP = 0.1
+F_E = 0.2
+
+
+@dataclass(frozen=True)
+class Material:
+    """Effective-atom description of a material (per-gram sums over elements)."""
+    name: str
+    rho: float          # nominal density, g/cm^3
+    zoa: float          # Z/A
+    i_ev: float         # mean excitation energy, eV
+    b: float            # sum w Z^2/A
+    ee: float           # sum w Z(Z+1)/A
+    p: float            # sum w Z^4/A
+
+    @property
+    def zs(self) -> float:
+        """Effective screening charge Z_s = B / (Z/A)."""
+        return self.b / self.zoa
+
+
+MATERIALS = (
+    Material("air", 0.0012, 0.4991, 85.7, 3.673, 4.172, 222.4),
+    # Lung: water composition at its own density.
+    Material("lung", 0.26, 0.5551, 75.0, 3.664, 4.219, 227.5),
+    Material("water", 1.00, 0.5551, 75.0, 3.664, 4.219, 227.5),
+    Material("bone", 1.85, 0.5148, 106.4, 5.420, 5.935, 1210.0),
+)
+MAT_AIR, MAT_LUNG, MAT_WATER, MAT_BONE = range(4)
+
+
+def energy_grid() -> np.ndarray:
+    """E_i = E_min (E_max/E_min)^(i/511), i = 0..511 (MeV)."""
+    i = np.arange(N_E, dtype=np.float64)
+    return E_MIN * (E_MAX / E_MIN) ** (i / (N_E - 1))
+
+
+# ----------------------------------------------------------------- photons
+
+def sigma_kn(e: float) -> float:
+    """Klein-Nishina total cross section per free electron (cm^2)."""
+    k = e / MC2
+    if k < 1e-4:
+        # Series about k = 0: sigma_T (1 - 2k + 26k^2/5 - ...), avoids cancellation.
+        return 8.0 * math.pi * R_E ** 2 / 3.0 * (1.0 - 2.0 * k + 5.2 * k * k - 13.3 * k ** 3)
+    l = math.log1p(2.0 * k)
+    t1 = (1.0 + k) / (k * k) * (2.0 * (1.0 + k) / (1.0 + 2.0 * k) - l / k)
+    t2 = l / (2.0 * k)
+    t3 = (1.0 + 3.0 * k) / (1.0 + 2.0 * k) ** 2
+    return 2.0 * math.pi * R_E ** 2 * (t1 + t2 - t3)
+
+
+def mu_compton(m: Material, e: float) -> float:
+    return N_A * m.zoa * sigma_kn(e)
+
+
+def mu_photo(m: Material, e: float) -> float:
+    return C_PE * m.p / e ** 3
+
+
+def mu_pair(m: Material, e: float) -> float:
+    thr = 2.0 * MC2
+    if e <= thr:
+        return 0.0
+    g = (1.0 - thr / e) ** 3 * math.log1p(e / thr)
+    return C_PP * m.b * g
+
+
+# --------------------------------------------------------------- electrons
+
+def _kin(t: float):
+    tau = t / MC2
+    pc = math.sqrt(t * (t + 2.0 * MC2))
+    beta2 = (pc / (t + MC2)) ** 2
+    return tau, pc, beta2
+
+
+def l_col(m: Material, t: float, w_cut: float | None) -> float:
+    """Bethe collision stopping power with Moller F-, restricted to energy losses
+    below w_cut (None: unrestricted).  No density effect."""
+    tau, _, beta2 = _kin(t)
+    dmax = t / 2.0
+    w = dmax if w_cut is None else min(w_cut, dmax)
+    d = w / MC2
+    i_mc2 = m.i_ev * 1e-6 / MC2
+    f = (-1.0 - beta2 + math.log((tau - d) * d) + tau / (tau - d)
+         + (d * d / 2.0 + (2.0 * tau + 1.0) * math.log1p(-d / tau)) / (tau + 1.0) ** 2)
+    pref = 2.0 * math.pi * R_E ** 2 * MC2 * N_A * m.zoa / beta2
+    return pref * (math.log(2.0 * (tau + 2.0) / i_mc2 ** 2) + f)
+
+
+def l_rad(m: Material, t: float, w_cut: float | None) -> float:
+    """Radiative stopping power of the flat W dsigma/dW model, restricted to W < w_cut."""
+    w = t if w_cut is None else min(w_cut, t)
+    return K_B * m.b * (t + MC2) / t * w
+
+
+def sigma_brems_hard(m: Material, t: float, w_cr: float) -> float:
+    if t <= w_cr:
+        return 0.0
+    return K_B * m.b * (t + MC2) / t * math.log(t / w_cr)
+
+
+def sigma_moller_hard(m: Material, t: float, w_cc: float) -> float:
+    if t <= 2.0 * w_cc:
+        return 0.0
+    tau, _, beta2 = _kin(t)
+    e0 = w_cc / t
+    g = tau / (tau + 1.0)
+    c = (2.0 * tau + 1.0) / (tau + 1.0) ** 2
+    br = 1.0 / e0 - 1.0 / (1.0 - e0) + g * g * (0.5 - e0) - c * math.log((1.0 - e0) / e0)
+    return N_A * m.zoa * 2.0 * math.pi * R_E ** 2 * MC2 / (beta2 * t) * br
+
+
+def screening_moliere(m: Material, t: float) -> float:
+    _, pc, beta2 = _kin(t)
+    beta = math.sqrt(beta2)
+    zs = m.zs
+    return 0.25 * (HBARC / (0.885 * A0 * pc)) ** 2 * zs ** (2.0 / 3.0) * (
+        1.13 + 3.76 * (ALPHA * zs / beta) ** 2)
+
+
+def lambda1_inv(m: Material, t: float) -> float:
+    """Transport cross section per gram of the screened-Rutherford (Wentzel) model."""
+    _, pc, beta2 = _kin(t)
+    a = screening_moliere(m, t)
+    k = (R_E * MC2 / (math.sqrt(beta2) * pc)) ** 2
+    return N_A * m.ee * 2.0 * math.pi * k * (math.log1p(1.0 / a) - 1.0 / (1.0 + a))
+
+
+def solve_a_hinge(kappa_step: float) -> float:
+    """Screening A of the hinge's Wentzel angle whose mean mu equals the Lewis
+    first moment of a step of kappa_step transport mean free paths:
+    A[(1+A) ln((1+A)/A) - 1] = (1 - exp(-kappa_step)) / 2."""
+    target = 0.5 * (1.0 - math.exp(-kappa_step))
+
+    def mean_mu(a):
+        return a * ((1.0 + a) * math.log((1.0 + a) / a) - 1.0)
+
+    return optimize.brentq(lambda a: mean_mu(a) - target, 1e-12, 10.0, xtol=1e-16, rtol=1e-15)
+
+
+# ------------------------------------------------------------------ tables
+
+@dataclass
+class Tables:
+    """FP64 tables for every material plus the scalars the transport needs."""
+    energies: np.ndarray
+    data: np.ndarray                     # [n_mat, N_Q, N_E]
+    materials: tuple = MATERIALS
+    e_abs_e: float = E_ABS_E
+    e_abs_g: float = E_ABS_G
+    w_cc: float = E_ABS_E
+    w_cr: float = E_ABS_G
+    kappa_step: float = KAPPA_STEP
+    f_e: float = F_E
+    a_hinge: float = 0.0
+    flags: int = 0
+
+    def to_blob(self) -> bytes:
+        return write_blob(self)
+
+
+def _range_table(m: Material, e: np.ndarray, lr) -> np.ndarray:
+    """R(E_i) = R_0 + int_{E_0}^{E_i} dT / L_r(T), R_0 = E_0 / L_r(E_0), by adaptive
+    quadrature over each grid interval (kinks of L_r are passed as break points)."""
+    kinks = (E_ABS_G, 2.0 * E_ABS_E)
+    r = np.empty_like(e)
+    r[0] = e[0] / lr(e[0])
+    for i in range(1, len(e)):
+        a, b = e[i - 1], e[i]
+        pts = [k for k in kinks if a < k < b]
+        val, err = integrate.quad(lambda t: 1.0 / lr(t), a, b, points=pts or None,
+                                  epsabs=0.0, epsrel=1e-13, limit=200)
+        r[i] = r[i - 1] + val
+    return r
+
+
+def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: float = KAPPA_STEP) -> Tables:
+    """Tabulate every quantity at the 512 grid nodes.
+
+    variant:
+      "standard"  restricted losses, hard Moller and bremsstrahlung events;
+      "no_hard"   no hard events: unrestricted stopping power, Sigma_M = Sigma_B = 0
+                  (the CSDA-track-length test case);
+      "pe_only"   standard electrons, photons interact only by photoabsorption.
+    """
+    e = energy_grid()
+    n_mat = len(materials)
+    data = np.zeros((n_mat, N_Q, N_E))
+    flags = 0
+    if variant == "no_hard":
+        flags |= FLAG_NO_HARD
+    elif variant == "pe_only":
+        flags |= FLAG_PE_ONLY
+    elif variant != "standard":
+        raise ValueError(f"unknown table variant {variant!r}")
+    w_cc = None if flags & FLAG_NO_HARD else E_ABS_E
+    w_cr = None if flags & FLAG_NO_HARD else E_ABS_G
+    for mi, m in enumerate(materials):
+        def lr(t, m=m):
+            return l_col(m, t, w_cc) + l_rad(m, t, w_cr)
+        for i, ei in enumerate(e):
+            if not flags & FLAG_PE_ONLY:
+                data[mi, Q_MU_C, i] = mu_compton(m, ei)
+                data[mi, Q_MU_PP, i] = mu_pair(m, ei)
+            data[mi, Q_MU_PE, i] = mu_photo(m, ei)
+            data[mi, Q_LAMBDA1_INV, i] = lambda1_inv(m, ei)
+            if not flags & FLAG_NO_HARD:
+                data[mi, Q_SIGMA_M, i] = sigma_moller_hard(m, ei, E_ABS_E)
+                data[mi, Q_SIGMA_B, i] = sigma_brems_hard(m, ei, E_ABS_G)
+            data[mi, Q_L_R, i] = lr(ei)
+        data[mi, Q_RANGE] = _range_table(m, e, lr)
+    return Tables(energies=e, data=data, materials=tuple(materials),
+                  kappa_step=kappa_step, a_hinge=solve_a_hinge(kappa_step), flags=flags)
+
+
+# -------------------------------------------------------------------- blob
+#
+# Little-endian layout:
+#   char[8]  magic "MCDTAB\0\1"
+#   u32      version, n_mat, n_e, n_q
+#   f64      e_min, e_max, e_abs_e, e_abs_g, w_cc, w_cr, kappa_step, f_e, a_hinge
+#   u32      flags, reserved
+#   n_mat x { char[16] name; f64 rho, zoa, i_ev, b, ee, p; f64 q[n_q][n_e] }
+
+_HDR = struct.Struct("<8s4I9d2I")
+_MAT = struct.Struct("<16s6d")
+
+
+def write_blob(t: Tables) -> bytes:
+    n_mat = t.data.shape[0]
+    out = bytearray(_HDR.pack(BLOB_MAGIC, BLOB_VERSION, n_mat, N_E, N_Q,
+                              t.energies[0], t.energies[-1], t.e_abs_e, t.e_abs_g,
+                              t.w_cc, t.w_cr, t.kappa_step, t.f_e, t.a_hinge, t.flags, 0))
+    for mi in range(n_mat):
+        m = t.materials[mi]
+        out += _MAT.pack(m.name.encode()[:15], m.rho, m.zoa, m.i_ev, m.b, m.ee, m.p)
+        out += np.ascontiguousarray(t.data[mi], dtype="<f8").tobytes()
+    return bytes(out)
+
+
+def read_blob(blob: bytes) -> Tables:
+    (magic, ver, n_mat, n_e, n_q, emin, emax, eae, eag, wcc, wcr, ks, fe, ah, flags,
+     _) = _HDR.unpack_from(blob, 0)
+    if magic != BLOB_MAGIC or ver != BLOB_VERSION or n_e != N_E or n_q != N_Q:
+        raise ValueError("not a version-1 table blob")
+    off = _HDR.size
+    mats, data = [], np.empty((n_mat, n_q, n_e))
+    for mi in range(n_mat):
+        name, rho, zoa, iev, b, ee, p = _MAT.unpack_from(blob, off)
+        off += _MAT.size
+        mats.append(Material(name.rstrip(b"\0").decode(), rho, zoa, iev, b, ee, p))
+        data[mi] = np.frombuffer(blob, dtype="<f8", count=n_q * n_e, offset=off).reshape(n_q, n_e)
+        off += 8 * n_q * n_e
+    return Tables(energies=energy_grid(), data=data, materials=tuple(mats), e_abs_e=eae,
+                  e_abs_g=eag, w_cc=wcc, w_cr=wcr, kappa_step=ks, f_e=fe, a_hinge=ah,
+                  flags=flags)
+
+
+_CACHE: dict = {}
+
+
+def standard_blob(variant: str = "standard", kappa_step: float = KAPPA_STEP) -> bytes:
+    """The blob for the four standard materials (memoised; generation takes ~1 s)."""
+    key = (variant, kappa_step)
+    if key not in _CACHE:
+        _CACHE[key] = build_tables(variant=variant, kappa_step=kappa_step).to_blob()
+    return _CACHE[key]

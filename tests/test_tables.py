@@ -1,0 +1,225 @@
+"""Pins of the synthetic physics tables (input data standing in for the paper's
+cross-section files, Sec. 2.2) against textbook values, independent forms of the
+same models and numerical integration of their differential cross sections."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+from paper_0910_0329_amd.inputs import tables as T
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_klein_nishina_textbook_values():
+    g = json.load(open(os.path.join(GOLD, "klein_nishina.json")))
+    for e, sb in g["values_barn"].items():
+        assert T.sigma_kn(float(e)) / 1e-24 == pytest.approx(sb, rel=g["rel_tol"])
+    assert T.sigma_kn(1e-7) / 1e-24 == pytest.approx(g["thomson_limit_barn"], rel=1e-6)
+    # the small-k series and the closed form agree where they hand over
+    k = 1.0e-4 * T.MC2
+    closed = T.sigma_kn(1.0001e-4 * T.MC2)
+    assert T.sigma_kn(k * 0.9999) == pytest.approx(closed, rel=1e-6)
+
+
+def test_kn_total_equals_integral_of_dcs():
+    """sigma_KN = int dsigma/dOmega dOmega with the Klein-Nishina angular law."""
+    for e in (0.05, 0.3, 2.0, 15.0):
+        k = e / T.MC2
+
+        def dcs(c):
+            r = 1.0 / (1.0 + k * (1.0 - c))
+            return math.pi * T.R_E ** 2 * r * r * (r + 1.0 / r - (1.0 - c * c))
+
+        val, _ = integrate.quad(dcs, -1.0, 1.0, epsrel=1e-12)
+        assert T.sigma_kn(e) == pytest.approx(val, rel=1e-9)
+
+
+def test_photon_coefficients_water():
+    w = T.MATERIALS[T.MAT_WATER]
+    assert T.mu_compton(w, 1.0) == pytest.approx(0.0706, rel=2e-3)
+    assert T.mu_photo(w, 0.1) == pytest.approx(2.76e-3, rel=2e-3)
+    assert T.mu_pair(w, 10.0) == pytest.approx(5.5e-3, rel=3e-3)
+    assert T.mu_pair(w, 2.0 * T.MC2) == 0.0
+    assert T.mu_pair(w, 1.0) == 0.0
+
+
+def test_bethe_restricted_reduces_to_unrestricted_form():
+    """With Delta = tau/2 the restricted F- equals the textbook unrestricted
+    F-(tau) = 1 - beta^2 + [tau^2/8 - (2 tau + 1) ln 2] / (tau + 1)^2, and the
+    prefactor 2 pi r_e^2 m c^2 N_A is 0.153536 MeV cm^2/g (ICRU 37)."""
+    w = T.MATERIALS[T.MAT_WATER]
+    for t in (0.01, 0.3, 1.0, 5.0, 20.0):
+        tau = t / T.MC2
+        beta2 = 1.0 - 1.0 / (tau + 1.0) ** 2
+        i_mc2 = w.i_ev * 1e-6 / T.MC2
+        fm = 1.0 - beta2 + (tau * tau / 8.0 - (2.0 * tau + 1.0) * math.log(2.0)) / (tau + 1.0) ** 2
+        s = 0.153536 * w.zoa / beta2 * (math.log(tau * tau * (tau + 2.0) / (2.0 * i_mc2 ** 2)) + fm)
+        assert T.l_col(w, t, None) == pytest.approx(s, rel=2e-5)
+    # 1 MeV water without density effect; ESTAR's 1.849 includes delta ~ 0.24
+    assert T.l_col(w, 1.0, None) == pytest.approx(1.8725, abs=5e-4)
+
+
+def test_restricted_loss_plus_hard_moller_is_unrestricted():
+    """Energy-loss bookkeeping of the Moller DCS: restricted stopping power plus
+    the first moment of the hard Moller DCS equals the unrestricted value."""
+    w = T.MATERIALS[T.MAT_WATER]
+    for t in (0.5, 2.0, 10.0, 20.0):
+        tau = t / T.MC2
+        beta2 = 1.0 - 1.0 / (tau + 1.0) ** 2
+        g = (tau / (tau + 1.0)) ** 2
+        c = (2.0 * tau + 1.0) / (tau + 1.0) ** 2
+        pref = T.N_A * w.zoa * 2.0 * math.pi * T.R_E ** 2 * T.MC2 / (beta2 * t)
+
+        def wdcs(eps):
+            return t * eps * pref * (1 / eps ** 2 + 1 / (1 - eps) ** 2 + g - c / (eps * (1 - eps)))
+
+        hard, _ = integrate.quad(wdcs, T.E_ABS_E / t, 0.5, epsrel=1e-12)
+        assert T.l_col(w, t, T.E_ABS_E) + hard == pytest.approx(T.l_col(w, t, None), rel=1e-9)
+
+
+def test_hard_cross_sections_are_integrals_of_their_dcs():
+    w = T.MATERIALS[T.MAT_WATER]
+    for t in (0.5, 3.0, 20.0):
+        tau = t / T.MC2
+        beta2 = 1.0 - 1.0 / (tau + 1.0) ** 2
+        g = (tau / (tau + 1.0)) ** 2
+        c = (2.0 * tau + 1.0) / (tau + 1.0) ** 2
+        pref = T.N_A * w.zoa * 2.0 * math.pi * T.R_E ** 2 * T.MC2 / (beta2 * t)
+        val, _ = integrate.quad(lambda e: pref * (1 / e ** 2 + 1 / (1 - e) ** 2 + g - c / (e * (1 - e))),
+                                T.E_ABS_E / t, 0.5, epsrel=1e-12)
+        assert T.sigma_moller_hard(w, t, T.E_ABS_E) == pytest.approx(val, rel=1e-9)
+        vb, _ = integrate.quad(lambda x: T.K_B * w.b * (t + T.MC2) / t / x, T.E_ABS_G, t, epsrel=1e-12)
+        assert T.sigma_brems_hard(w, t, T.E_ABS_G) == pytest.approx(vb, rel=1e-9)
+    assert T.sigma_moller_hard(w, 0.4, T.E_ABS_E) == 0.0
+
+
+def test_transport_cross_section_is_first_moment_of_wentzel_dcs():
+    w = T.MATERIALS[T.MAT_WATER]
+    for t in (0.2, 1.0, 20.0):
+        _, pc, beta2 = T._kin(t)
+        a = T.screening_moliere(w, t)
+        k = (T.R_E * T.MC2 / (math.sqrt(beta2) * pc)) ** 2
+        # dsigma/dOmega = Z(Z+1) k / (1 - cos + 2A)^2 per atom -> per gram with Ee
+        f = lambda x: 2 * math.pi * x * T.N_A * w.ee * k / (x + 2 * a) ** 2
+        val, _ = integrate.quad(f, 0.0, 2.0, points=[2 * a, 20 * a], epsrel=1e-11, limit=400)
+        assert T.lambda1_inv(w, t) == pytest.approx(val, rel=1e-8)
+    # sizing: lambda_1 in water ~ 0.042, 0.51, 6.8, 79 cm at 0.2, 1, 5, 20 MeV
+    for t, lam in ((0.2, 0.042), (1.0, 0.51), (5.0, 6.8), (20.0, 79.0)):
+        assert 1.0 / T.lambda1_inv(w, t) == pytest.approx(lam, rel=0.02)
+
+
+def test_a_hinge_solves_lewis_first_moment():
+    a = T.solve_a_hinge(0.1)
+    assert a == pytest.approx(0.0143284, rel=1e-5)
+    # mean of mu = (1 - cos)/2 under p(mu) ~ 1/(mu + A)^2 on [0, 1], by quadrature
+    num, _ = integrate.quad(lambda m: m / (m + a) ** 2, 0, 1, points=[a], epsrel=1e-12)
+    den, _ = integrate.quad(lambda m: 1 / (m + a) ** 2, 0, 1, points=[a], epsrel=1e-12)
+    assert num / den == pytest.approx(0.5 * (1 - math.exp(-0.1)), rel=1e-9)
+
+
+def test_range_table_against_independent_quadrature(tabs):
+    """R(E_i) from the tables vs a log-space Simpson integration of 1/L_r."""
+    w = T.MATERIALS[T.MAT_WATER]
+    lr = lambda t: T.l_col(w, t, T.E_ABS_E) + T.l_rad(w, t, T.E_ABS_G)
+    e = tabs.energies
+    for i in (100, 300, 400, 511):
+        # split at the kinks of L_r so the smooth pieces integrate to high order
+        bounds = sorted({e[0], e[i]} | {k for k in (T.E_ABS_G, 2 * T.E_ABS_E) if e[0] < k < e[i]})
+        tot = e[0] / lr(e[0])
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            x = np.linspace(math.log(a), math.log(b), 20001)
+            y = np.exp(x) / np.array([lr(v) for v in np.exp(x)])
+            tot += integrate.simpson(y, x=x)
+        assert tabs.data[T.MAT_WATER, T.Q_RANGE, i] == pytest.approx(tot, rel=1e-8)
+    # sizing: restricted range 0.2 -> 20 MeV in water ~ 10.38 g/cm^2
+    r = np.interp(np.log([0.2, 20.0]), np.log(e), tabs.data[T.MAT_WATER, T.Q_RANGE])
+    assert r[1] - r[0] == pytest.approx(10.38, rel=2e-3)
+
+
+def test_range_is_monotone_and_density_scaled_materials_match(tabs):
+    for m in range(4):
+        assert np.all(np.diff(tabs.data[m, T.Q_RANGE]) > 0)
+        assert np.all(tabs.data[m] >= 0)
+    # lung is water composition: identical per-gram tables
+    np.testing.assert_array_equal(tabs.data[T.MAT_LUNG], tabs.data[T.MAT_WATER])
+
+
+def test_blob_roundtrip_and_validation(blob):
+    t = T.read_blob(blob)
+    assert t.data.shape == (4, 8, 512)
+    assert T.write_blob(t) == blob
+    assert oracle.blob_check(blob) == 4
+    assert oracle.blob_check(blob[:-8]) == -1
+    bad = bytearray(blob)
+    bad[0] = ord("X")
+    assert oracle.blob_check(bytes(bad)) == -1
+    # a non-monotone range table is rejected
+    t2 = T.read_blob(blob)
+    t2.data[2, T.Q_RANGE, 10] = t2.data[2, T.Q_RANGE, 9]
+    assert oracle.blob_check(T.write_blob(t2)) == -1
+    t3 = T.read_blob(blob)
+    t3.data[1, T.Q_MU_C, 5] = -1.0
+    assert oracle.blob_check(T.write_blob(t3)) == -1
+
+
+def test_oracle_interpolation_matches_nodes_and_is_linear_in_log_e(blob, tabs):
+    e = tabs.energies
+    for q in range(8):
+        for i in (0, 17, 255, 511):
+            assert oracle.interp(blob, 2, q, e[i]) == pytest.approx(tabs.data[2, q, i], rel=1e-12, abs=1e-300)
+    # midpoint in ln E is the mean of the two nodes
+    i = 200
+    em = math.sqrt(e[i] * e[i + 1])
+    assert oracle.interp(blob, 3, T.Q_MU_C, em) == pytest.approx(
+        0.5 * (tabs.data[3, T.Q_MU_C, i] + tabs.data[3, T.Q_MU_C, i + 1]), rel=1e-12)
+    # clamped outside the grid
+    assert oracle.interp(blob, 2, T.Q_RANGE, 100.0) == pytest.approx(tabs.data[2, T.Q_RANGE, 511])
+    # the range inverse inverts the interpolant
+    for t in (0.2, 0.73, 4.4, 19.9):
+        r = oracle.interp(blob, 2, T.Q_RANGE, t)
+        assert oracle.range_inverse(blob, 2, r) == pytest.approx(t, rel=1e-12)
+
+
+def test_majorant_bounds_every_voxel(blob, tabs):
+    from paper_0910_0329_amd.inputs import phantoms
+    ph = phantoms.random_field_phantom(24, 0.5, seed=7)
+    mu = oracle.majorant(blob, ph)
+    rng = np.random.default_rng(0)
+    ln_e = np.log(tabs.energies)
+    es = np.exp(rng.uniform(math.log(1e-3), math.log(20.0), 2000))
+    tot = tabs.data[:, 0] + tabs.data[:, 1] + tabs.data[:, 2]
+    for m in range(4):
+        sel = ph.mat == m
+        if not sel.any():
+            continue
+        rmax = float(ph.rho[sel].max())
+        for e in es[:200]:
+            mu_loc = rmax * np.interp(math.log(e), ln_e, tot[m])
+            assert np.interp(math.log(e), ln_e, mu) >= mu_loc * (1 - 1e-12)
+    # and it is attained: at every node some material sets it exactly
+    best = np.max([float(ph.rho[ph.mat == m].max()) * tot[m] for m in range(4) if (ph.mat == m).any()], axis=0)
+    np.testing.assert_allclose(mu, best, rtol=1e-15)
+
+
+def test_random_field_phantom_statistics():
+    from paper_0910_0329_amd.inputs import phantoms
+    ph = phantoms.random_field_phantom(64, 0.5, seed=51)
+    frac = np.bincount(ph.mat.ravel(), minlength=4) / ph.n_vox
+    # thresholds 0.1/0.5/1.3 on N(0.9, 0.45^2): 3.8 / 14.9 / 62.6 / 18.7 %
+    np.testing.assert_allclose(frac, [0.038, 0.149, 0.626, 0.187], atol=0.03)
+    assert ph.rho.min() >= 0.0012 and ph.rho.max() <= 2.0
+    ph2 = phantoms.random_field_phantom(64, 0.5, seed=51)
+    np.testing.assert_array_equal(ph.rho, ph2.rho)
+
+
+def test_spectrum_mean():
+    from paper_0910_0329_amd.inputs import sources
+    edges, w = sources.spectrum_6mv()
+    assert len(w) == 64
+    s = sources.Source(energy_kind=sources.HISTOGRAM, edges=edges, weights=w)
+    assert s.mean_energy() == pytest.approx(2.067, abs=2e-3)
