@@ -1,0 +1,181 @@
+/*
+ * mcdose: coupled electron-photon Monte Carlo dose engine for AMD Instinct
+ * MI355X (gfx950).  C ABI of libmcdose.so.
+ *
+ * The engine computes what Jia et al. (arXiv:0910.0329) move to a GPU: the DPM
+ * transport scheme of Sec. 2.1 (Woodcock photon tracking; condensed-history
+ * electrons with continuous slowing down below the production thresholds and
+ * detailed hard Moller/bremsstrahlung events above them) run history by
+ * history as in the flow of Fig. 1 / Sec. 2.2, with a per-history local
+ * counter collected into a global dose counter (Sec. 2.4) and the uncertainty
+ * estimate of Sec. 3.
+ *
+ * Conventions
+ *   - Units: cm, MeV, g, g/cm^3; dose in Gy per source history.
+ *   - Voxel arrays are x-fastest: v = (k * ny + j) * nx + i.
+ *   - Every function returns an mcd_status (0 = OK, negative = error); on
+ *     error no output is written and mcd_last_error() explains it.  No C++
+ *     exception or abort crosses this interface.
+ *   - Host pointers are read during the call and may be freed on return.
+ *   - Device pointers are HIP device addresses on the context's device.
+ *   - A context is not thread-safe except for the serving calls
+ *     (mcd_submit / mcd_poll / mcd_wait / mcd_cancel), which may be called
+ *     from any thread.
+ */
+#ifndef MCDOSE_H
+#define MCDOSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MCD_OK = 0,
+    MCD_E_INVAL = -1,     /* invalid argument (sizes, ranges, table or phantom content) */
+    MCD_E_NOMEM = -2,     /* device allocation failed or would exceed the HBM budget */
+    MCD_E_NOTFOUND = -3,  /* unknown table, phantom or ticket handle */
+    MCD_E_OVERFLOW = -4,  /* particle stack or per-history local counter overflowed */
+    MCD_E_DEVICE = -5,    /* HIP runtime error (message in mcd_last_error) */
+    MCD_E_BUSY = -6,      /* request not finished yet */
+    MCD_E_CANCELED = -7   /* request was cancelled */
+} mcd_status;
+
+typedef struct mcd_ctx mcd_ctx;
+
+/* Voxel grid: nx*ny*nz voxels of dx*dy*dz cm; the box spans
+ * [x0, x0 + nx dx) x [y0, y0 + ny dy) x [z0, z0 + nz dz); its top face z = z0
+ * faces the source. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy, dz;
+    double x0, y0, z0;
+} mcd_grid;
+
+enum { MCD_PHOTON = 0, MCD_ELECTRON = 1, MCD_POSITRON = 2 };
+enum { MCD_MONO = 0, MCD_HISTOGRAM = 1 };
+enum { MCD_PENCIL = 0, MCD_POINT_FIELD = 1 };
+#define MCD_MAX_BINS 64
+
+/* Source model (Sec. 3: point sources with a rectangular field, a
+ * monoenergetic electron beam or a photon spectrum).
+ *   pencil      enters the top face at (pos[0], pos[1]) along +z;
+ *   point-field from the point pos towards a point drawn uniformly on the
+ *               rectangle centred at (field[0], field[1]) with half-widths
+ *               (field[2], field[3]) on the plane z = z0; primaries whose
+ *               entry point is outside the top face miss the phantom.
+ * Energies: mono e0, or a histogram of n_bins bins (edges[0..n_bins],
+ * weights[0..n_bins-1], any positive scale); 0 < E <= 20 MeV. */
+typedef struct {
+    int32_t particle;      /* MCD_PHOTON, MCD_ELECTRON, MCD_POSITRON */
+    int32_t energy_kind;   /* MCD_MONO, MCD_HISTOGRAM */
+    int32_t beam_kind;     /* MCD_PENCIL, MCD_POINT_FIELD */
+    int32_t n_bins;
+    double e0;
+    double pos[3];
+    double field[4];
+    double edges[MCD_MAX_BINS + 1];
+    double weights[MCD_MAX_BINS];
+} mcd_source;
+
+/* Energy bookkeeping of a run, MeV (FP64 sums on the device). */
+typedef struct {
+    double e_src;    /* source energy (a positron counts T + 2 m c^2) */
+    double e_csda;   /* continuous-slowing-down deposits */
+    double e_local;  /* below-cutoff deposits on the spot */
+    double e_esc;    /* energy carried out of the box */
+    double e_miss;   /* primaries that missed the phantom */
+    double track_e;  /* total electron path length, cm */
+} mcd_energy_balance;
+
+/* Event counters (filled when mcd_opts.diagnostics != 0). */
+enum {
+    MCD_C_HISTORIES, MCD_C_FLIGHTS, MCD_C_VIRTUAL, MCD_C_COMPTON, MCD_C_PHOTO, MCD_C_PAIR,
+    MCD_C_SEGMENTS, MCD_C_SEG_E, MCD_C_SEG_H, MCD_C_SEG_K, MCD_C_SEG_B, MCD_C_SEG_F,
+    MCD_C_HINGES, MCD_C_MOLLER, MCD_C_BREMS, MCD_C_SPAWNS, MCD_C_PHILOX, MCD_C_FLUSHES,
+    MCD_C_ESCAPES, MCD_C_MISSES, MCD_C_LOCAL, MCD_C_VOID, MCD_C_COMPTON_TRIES,
+    MCD_C_MOLLER_TRIES, MCD_C_MAX_STACK, MCD_NCOUNT = 32
+};
+
+/* Per-history diagnostic record (mcd_opts.history_records). */
+typedef struct {
+    double edep;          /* energy deposited by the history, MeV */
+    double track_e;       /* electron path length of the history, cm */
+    uint64_t hash;        /* order-independent hash of its particles' event sequences */
+    uint32_t n_particles;
+    uint32_t escaped;
+} mcd_history_record;
+
+/* Run options; NULL means defaults.  None of them changes the physics: results
+ * depend only on (tables, phantom, source, history range, seed, request key). */
+typedef struct {
+    uint64_t first_history;   /* histories [first_history, first_history + n) */
+    int32_t block_size;       /* threads per block, 0 = tuned default */
+    int32_t grid_blocks;      /* blocks, 0 = enough to fill the device */
+    int32_t stack_depth;      /* particle stack per lane, 0 = default (64) */
+    int32_t tally_slots;      /* per-history local counter slots (power of 2), 0 = default (1024) */
+    int32_t diagnostics;      /* 1: fill counters (slower kernel variant) */
+    int32_t accumulate;       /* 1: add to the tallies of the previous call instead of clearing */
+    void* history_records;    /* device array of n mcd_history_record, or NULL */
+} mcd_opts;
+
+/* Output of a run.  dose and sigma (nx*ny*nz doubles each, Gy per source
+ * history) and S, Q (raw tallies: sum over histories of the per-history
+ * energy in a voxel and of its square, MeV and MeV^2) are caller-allocated
+ * and optional (NULL to skip); they are device pointers when on_device != 0,
+ * host pointers otherwise.  The scalars are filled on return. */
+typedef struct {
+    double* dose;
+    double* sigma;
+    double* S;
+    double* Q;
+    int32_t on_device;
+    mcd_energy_balance eb;
+    uint64_t counters[MCD_NCOUNT];
+    double dmax;          /* maximum dose, Gy per history */
+    double sigma_bar;     /* mean sigma/D over voxels with D > dmax / 2 (Sec. 3) */
+    double kernel_ms;     /* device time of the transport kernel(s) */
+    double total_ms;      /* device time from tally clear to finalisation */
+} mcd_result;
+
+/* Creates a context on HIP device `device`.  hbm_budget_bytes caps what the
+ * context allocates (0: 90% of the free device memory at creation). */
+int mcd_create(int device, uint64_t hbm_budget_bytes, mcd_ctx** out);
+int mcd_destroy(mcd_ctx* ctx);
+
+/* Loads a physics table blob (cross sections per interaction, material and
+ * energy, Sec. 2.2; format: magic "MCDTAB\0\1", version 1, 512-node log grid
+ * from 1 keV to 20 MeV, 8 quantities per material).  The blob is validated
+ * (sizes, monotone ranges, non-negative finite values, scalar ranges) and
+ * converted to FP32 device tables.  *out_tables receives a handle. */
+int mcd_load_materials(mcd_ctx* ctx, const void* blob, size_t nbytes, int32_t* out_tables);
+int mcd_unload_materials(mcd_ctx* ctx, int32_t tables);
+
+/* Uploads a voxel phantom (material index per voxel, u8, < number of
+ * materials; density per voxel, f32 > 0; both host arrays of nx*ny*nz) bound
+ * to a table set, and builds its Woodcock majorant.  The phantom stays
+ * resident until unloaded.  *out_phantom receives a handle. */
+int mcd_load_phantom(mcd_ctx* ctx, const mcd_grid* grid, const uint8_t* mat, const float* rho,
+                     int32_t tables, int32_t* out_phantom);
+int mcd_unload_phantom(mcd_ctx* ctx, int32_t phantom);
+
+/* Transports n_histories source histories through a phantom and returns the
+ * dose and its uncertainty (Fig. 1 flow: source particle, transport, secondary
+ * stack, dose collection).  seed and request_key key the Philox4x32-10 streams
+ * (seed < 2^32, request_key < 2^32, first_history + n_histories <= 2^32).
+ * Blocking: returns when the results are in `out`.  hip_stream may be a
+ * hipStream_t (e.g. torch's current stream) or NULL for the context's stream. */
+int mcd_simulate(mcd_ctx* ctx, int32_t phantom, const mcd_source* src, uint64_t n_histories,
+                 uint64_t seed, uint32_t request_key, const mcd_opts* opts, mcd_result* out,
+                 void* hip_stream);
+
+/* Status and error text. */
+const char* mcd_status_string(int status);
+const char* mcd_last_error(mcd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

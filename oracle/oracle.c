@@ -637,8 +637,8 @@ static void transport_electron(ctx* c, stream* s, int type, double T, double r[3
         double sh = interp(t, tab(t, m, Q_SM), T) + interp(t, tab(t, m, Q_SB), T);
         /* the five step limits, ties resolved in the order E, h, kappa, b, f */
         double l_e = fmax(0.0, (rt - c->r_abs[m]) / rho);
-        double l_h = sh > 0.0 ? n_h / (rho * sh) : INFINITY;
-        double l_k = kap / (rho * lam);
+        double l_h = sh > 0.0 ? fmax(0.0, n_h / (rho * sh)) : INFINITY;
+        double l_k = fmax(0.0, kap / (rho * lam));
         int axis;
         double l_b = boundary_distance(G, r, d, idx, &axis);
         double l_f = (rt - interp(t, R, (1.0 - t->f_e) * T)) / rho;

@@ -1,0 +1,218 @@
+"""Python binding of libmcdose (the C ABI declared in include/mcdose.h).
+
+Argument marshalling only: every step of the transport, tally and
+finalisation runs in the HIP library.  PyTorch provides device memory and the
+stream the library runs on.  The library must have been built
+(`python -m paper_0910_0329_amd.build`); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmcdose.so")
+
+OK, E_INVAL, E_NOMEM, E_NOTFOUND, E_OVERFLOW, E_DEVICE, E_BUSY, E_CANCELED = 0, -1, -2, -3, -4, -5, -6, -7
+NCOUNT = 32
+COUNT_NAMES = ("histories", "flights", "virtual", "compton", "photo", "pair", "segments",
+               "seg_E", "seg_h", "seg_k", "seg_b", "seg_f", "hinges", "moller", "brems",
+               "spawns", "philox", "flushes", "escapes", "misses", "local", "void",
+               "compton_tries", "moller_tries", "max_stack")
+
+
+class McdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double)]
+
+
+class Source(C.Structure):
+    _fields_ = [("particle", C.c_int32), ("energy_kind", C.c_int32), ("beam_kind", C.c_int32),
+                ("n_bins", C.c_int32), ("e0", C.c_double), ("pos", C.c_double * 3),
+                ("field", C.c_double * 4), ("edges", C.c_double * 65),
+                ("weights", C.c_double * 64)]
+
+
+class EnergyBalance(C.Structure):
+    _fields_ = [("e_src", C.c_double), ("e_csda", C.c_double), ("e_local", C.c_double),
+                ("e_esc", C.c_double), ("e_miss", C.c_double), ("track_e", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("first_history", C.c_uint64), ("block_size", C.c_int32),
+                ("grid_blocks", C.c_int32), ("stack_depth", C.c_int32),
+                ("tally_slots", C.c_int32), ("diagnostics", C.c_int32),
+                ("accumulate", C.c_int32), ("history_records", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("dose", C.c_void_p), ("sigma", C.c_void_p), ("S", C.c_void_p), ("Q", C.c_void_p),
+                ("on_device", C.c_int32), ("eb", EnergyBalance),
+                ("counters", C.c_uint64 * NCOUNT), ("dmax", C.c_double),
+                ("sigma_bar", C.c_double), ("kernel_ms", C.c_double), ("total_ms", C.c_double)]
+
+
+HISTORY_DTYPE = np.dtype([("edep", "<f8"), ("track_e", "<f8"), ("hash", "<u8"),
+                          ("n_particles", "<u4"), ("escaped", "<u4")])
+
+_lib = None
+
+
+def lib():
+    """Loads libmcdose.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_0910_0329_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32 = C.c_void_p, C.c_int32
+        L.mcd_create.argtypes = [C.c_int, C.c_uint64, C.POINTER(vp)]
+        L.mcd_destroy.argtypes = [vp]
+        L.mcd_load_materials.argtypes = [vp, vp, C.c_size_t, C.POINTER(i32)]
+        L.mcd_unload_materials.argtypes = [vp, i32]
+        L.mcd_load_phantom.argtypes = [vp, C.POINTER(Grid), vp, vp, i32, C.POINTER(i32)]
+        L.mcd_unload_phantom.argtypes = [vp, i32]
+        L.mcd_simulate.argtypes = [vp, i32, C.POINTER(Source), C.c_uint64, C.c_uint64, C.c_uint32,
+                                   C.POINTER(Opts), C.POINTER(Result), vp]
+        L.mcd_status_string.argtypes = [C.c_int]
+        L.mcd_status_string.restype = C.c_char_p
+        L.mcd_last_error.argtypes = [vp]
+        L.mcd_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("mcd_create", "mcd_destroy", "mcd_load_materials", "mcd_unload_materials",
+            "mcd_load_phantom", "mcd_unload_phantom", "mcd_simulate", "mcd_status_string",
+            "mcd_last_error")
+
+
+def make_source(src) -> Source:
+    s = Source()
+    s.particle, s.energy_kind, s.beam_kind = src.particle, src.energy_kind, src.beam_kind
+    s.n_bins = src.n_bins if src.energy_kind == 1 else 0
+    s.e0 = src.e0
+    for i in range(3):
+        s.pos[i] = src.pos[i]
+    for i in range(4):
+        s.field[i] = src.field_rect[i]
+    if src.energy_kind == 1:
+        for i, v in enumerate(src.edges):
+            s.edges[i] = v
+        for i, v in enumerate(src.weights):
+            s.weights[i] = v
+    return s
+
+
+def make_opts(**kw) -> Opts:
+    o = Opts()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return getattr(stream, "cuda_stream", stream)
+
+
+class Engine:
+    """One mcdose context on one GPU."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        self._h = C.c_void_p()
+        self._check(lib().mcd_create(device, hbm_budget, C.byref(self._h)), "mcd_create")
+        self.device = device
+
+    def _check(self, rc, what):
+        if rc != OK:
+            msg = lib().mcd_last_error(self._h).decode() if self._h else lib().mcd_status_string(rc).decode()
+            raise McdError(rc, f"{what}: {msg}")
+
+    def close(self):
+        if self._h:
+            lib().mcd_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def load_materials(self, blob: bytes) -> int:
+        out = C.c_int32()
+        self._check(lib().mcd_load_materials(self._h, blob, len(blob), C.byref(out)), "mcd_load_materials")
+        return out.value
+
+    def unload_materials(self, t: int):
+        self._check(lib().mcd_unload_materials(self._h, t), "mcd_unload_materials")
+
+    def load_phantom(self, ph, tables: int) -> int:
+        g = Grid(ph.nx, ph.ny, ph.nz, ph.dx, ph.dy, ph.dz, ph.x0, ph.y0, ph.z0)
+        mat = np.ascontiguousarray(ph.mat, dtype=np.uint8)
+        rho = np.ascontiguousarray(ph.rho, dtype=np.float32)
+        out = C.c_int32()
+        self._check(lib().mcd_load_phantom(self._h, C.byref(g), mat.ctypes.data, rho.ctypes.data,
+                                           tables, C.byref(out)), "mcd_load_phantom")
+        return out.value
+
+    def unload_phantom(self, p: int):
+        self._check(lib().mcd_unload_phantom(self._h, p), "mcd_unload_phantom")
+
+    def simulate(self, phantom: int, src, n: int, seed: int, key: int = 0, *, n_vox: int = None,
+                 device_out: bool = True, want_dose: bool = True, want_tallies: bool = False,
+                 stream=None, history_records=None, **opts) -> dict:
+        """Runs histories and returns dose, sigma (torch CUDA tensors when
+        device_out, numpy otherwise), the raw tallies if asked, the energy
+        balance, counters, Dmax, sigma-bar and device timings."""
+        s = make_source(src)
+        o = make_opts(**opts)
+        if history_records is not None:
+            o.history_records = history_records.data_ptr()
+            o.diagnostics = 1
+        r = Result()
+        bufs = {}
+        if n_vox is None and (want_dose or want_tallies):
+            raise ValueError("n_vox is required for dose or tally outputs")
+        names = (("dose", "sigma") if want_dose else ()) + (("S", "Q") if want_tallies else ())
+        if device_out:
+            import torch
+            for nm in names:
+                bufs[nm] = torch.empty(n_vox, dtype=torch.float64, device=f"cuda:{self.device}")
+                setattr(r, nm, bufs[nm].data_ptr())
+            r.on_device = 1
+            if stream is None:
+                stream = torch.cuda.current_stream(self.device)
+        else:
+            for nm in names:
+                bufs[nm] = np.empty(n_vox, dtype=np.float64)
+                setattr(r, nm, bufs[nm].ctypes.data)
+            r.on_device = 0
+        rc = lib().mcd_simulate(self._h, phantom, C.byref(s), n, seed, key, C.byref(o), C.byref(r),
+                                _stream_ptr(stream))
+        self._check(rc, "mcd_simulate")
+        eb = r.eb
+        out = dict(bufs)
+        out.update({
+            "bal": {"E_src": eb.e_src, "E_csda": eb.e_csda, "E_local": eb.e_local,
+                    "E_esc": eb.e_esc, "E_miss": eb.e_miss, "track_e": eb.track_e},
+            "cnt": dict(zip(COUNT_NAMES, (int(x) for x in r.counters))),
+            "dmax": r.dmax, "sigma_bar": r.sigma_bar, "kernel_ms": r.kernel_ms,
+            "total_ms": r.total_ms, "n": n,
+        })
+        return out
