@@ -115,10 +115,14 @@ typedef struct {
     int32_t block_size;       /* threads per block, 0 = tuned default */
     int32_t grid_blocks;      /* blocks, 0 = enough to fill the device */
     int32_t stack_depth;      /* particle stack per lane, 0 = default (64) */
-    int32_t tally_slots;      /* per-history local counter slots (power of 2), 0 = default (1024) */
+    int32_t tally_slots;      /* per-history local counter slots (power of 2), 0 = default (512) */
     int32_t diagnostics;      /* 1: fill counters (slower kernel variant) */
     int32_t accumulate;       /* 1: add to the tallies of the previous call instead of clearing */
     void* history_records;    /* device array of n mcd_history_record, or NULL */
+    int32_t lockstep;         /* measurement mode: all 64 lanes of a wave replay the same history,
+                                 so the wave executes that history's instruction path without
+                                 divergence; tallies and balance then count each history 64 times */
+    int32_t reserved;
 } mcd_opts;
 
 /* Output of a run.  dose and sigma (nx*ny*nz doubles each, Gy per source

@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -22,6 +23,24 @@ HIPCC_FLAGS = [
 ]
 
 
+# Production (non-diagnostic) transport kernels: checked for private scratch.
+HOT_KERNELS = ("_ZN3mcd11k_transportILb0EEEvNS_7KParamsE",)
+
+
+def resource_usage(remarks: str) -> dict:
+    """Per-kernel register/scratch usage from hipcc's kernel-resource-usage remarks."""
+    out, cur = {}, None
+    for line in remarks.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = out.setdefault(m.group(1), {})
+            continue
+        m = re.search(r"remark:\s+([A-Za-z ]+?)(?: \[bytes/lane\])?: (\d+)", line)
+        if m and cur is not None:
+            cur[m.group(1).replace(" ", "")] = int(m.group(2))
+    return out
+
+
 def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
@@ -33,12 +52,20 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc(), *HIPCC_FLAGS, "-Rpass-analysis=kernel-resource-usage", "-I", INCLUDE,
+               "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
-        if verbose and r.stderr:
-            print(r.stderr, file=sys.stderr)
+        usage = resource_usage(r.stderr)
+        if verbose:
+            for k, v in usage.items():
+                print(k, v, file=sys.stderr)
+        for name, u in usage.items():
+            # the production transport kernels must keep their state in registers:
+            # private scratch in the step loop costs several times the runtime
+            if name in HOT_KERNELS and u.get("ScratchSize", 0) > 0:
+                raise RuntimeError(f"{name} uses {u['ScratchSize']} bytes/lane of private scratch")
         return obj
 
     with ThreadPoolExecutor(len(SOURCES)) as ex:

@@ -58,6 +58,7 @@ struct KParams {
     char* scratch;           // per-lane stack and local counter
     int stack_depth;
     int slots;               // local counter slots, power of two
+    int lockstep;            // 1: all lanes of a wave run the same history
     size_t lane_bytes;
     void* hist;              // mcd_history_record[n] or null
 };

@@ -771,7 +771,8 @@ __global__ __launch_bounds__(512) void k_transport(KParams p)
     Part q;
     q.type = DEAD;
     bool have = false;
-    uint32_t off = 0;
+    uint32_t off = 0, rounds = 0;
+    const size_t n_lanes = (size_t)gridDim.x * blockDim.x;
     for (;;) {
         if (q.type == DEAD) {
             if (L.sp > 0) {
@@ -783,7 +784,16 @@ __global__ __launch_bounds__(512) void k_transport(KParams p)
                     have = false;
                 }
                 if (L.failed || __atomic_load_n(p.err, __ATOMIC_RELAXED)) break;
-                const unsigned long long o = atomicAdd(p.next, 1ull);
+                unsigned long long o;
+                if (p.lockstep) {
+                    // every lane of a wave takes the same history (a static
+                    // round-robin over waves): the wave then runs that
+                    // history's instruction path without divergence
+                    o = (unsigned long long)(lane_id >> 6) + (unsigned long long)rounds * (n_lanes >> 6);
+                    ++rounds;
+                } else {
+                    o = atomicAdd(p.next, 1ull);
+                }
                 if (o >= (unsigned long long)p.n) break;
                 off = (uint32_t)o;
                 have = true;

@@ -573,6 +573,8 @@ int mcd_simulate(mcd_ctx* c, int32_t phantom, const mcd_source* src, uint64_t n_
     p.slots = slots;
     p.lane_bytes = c->lane_bytes;
     p.hist = diag && opts ? opts->history_records : nullptr;
+    p.lockstep = opts && opts->lockstep ? 1 : 0;
+    if (p.lockstep && (threads & 63)) return c->fail(MCD_E_INVAL, "lockstep needs whole waves");
     if (p.hist && !diag) return c->fail(MCD_E_INVAL, "history records need diagnostics");
     double* red = (double*)(c->small + kOffRed);
 

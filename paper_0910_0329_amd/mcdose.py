@@ -51,7 +51,8 @@ class Opts(C.Structure):
     _fields_ = [("first_history", C.c_uint64), ("block_size", C.c_int32),
                 ("grid_blocks", C.c_int32), ("stack_depth", C.c_int32),
                 ("tally_slots", C.c_int32), ("diagnostics", C.c_int32),
-                ("accumulate", C.c_int32), ("history_records", C.c_void_p)]
+                ("accumulate", C.c_int32), ("history_records", C.c_void_p),
+                ("lockstep", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Result(C.Structure):
