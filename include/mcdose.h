@@ -108,28 +108,49 @@ typedef struct {
     uint32_t escaped;
 } mcd_history_record;
 
-/* Run options; NULL means defaults.  None of them changes the physics: results
- * depend only on (tables, phantom, source, history range, seed, request key). */
+/* Transport kernels.
+ *   MCD_KERNEL_REGROUPED  particles regrouped by type into photon and electron
+ *                         phases with device queues; batch statistics (the
+ *                         histories form 16 groups, history mod 16, and sigma
+ *                         comes from the spread of the group means).
+ *   MCD_KERNEL_PLAIN      one lane per history with its own secondary stack
+ *                         and an exact history-by-history local counter
+ *                         (sigma from the per-history second moment).      */
+enum { MCD_KERNEL_REGROUPED = 0, MCD_KERNEL_PLAIN = 1 };
+
+/* Run options; NULL means defaults.  None of them changes which histories are
+ * simulated or how: the histories depend only on (tables, phantom, source,
+ * history range, seed, request key); the kernel choice selects the
+ * uncertainty estimator and the tally precision selects FP64 or FP32 sums. */
 typedef struct {
     uint64_t first_history;   /* histories [first_history, first_history + n) */
     int32_t block_size;       /* threads per block, 0 = tuned default */
     int32_t grid_blocks;      /* blocks, 0 = enough to fill the device */
     int32_t stack_depth;      /* particle stack per lane, 0 = default (64) */
-    int32_t tally_slots;      /* per-history local counter slots (power of 2), 0 = default (512) */
+    int32_t tally_slots;      /* plain kernel: local counter slots (power of 2), 0 = 512 */
     int32_t diagnostics;      /* 1: fill counters (slower kernel variant) */
     int32_t accumulate;       /* 1: add to the tallies of the previous call instead of clearing */
     void* history_records;    /* device array of n mcd_history_record, or NULL */
-    int32_t lockstep;         /* measurement mode: all 64 lanes of a wave replay the same history,
-                                 so the wave executes that history's instruction path without
-                                 divergence; tallies and balance then count each history 64 times */
-    int32_t reserved;
+    int32_t lockstep;         /* plain kernel, measurement mode: all 64 lanes of a wave replay the
+                                 same history, so the wave executes that history's instruction
+                                 path without divergence; tallies then count each history 64 times */
+    int32_t kernel;           /* MCD_KERNEL_REGROUPED (default) or MCD_KERNEL_PLAIN */
+    int32_t tally_fp32;       /* regrouped kernel: FP32 instead of FP64 dose accumulators */
+    int32_t chunk_per_lane;   /* regrouped kernel: new histories per lane and cycle, 0 = 16 */
+    int32_t use_graph;        /* regrouped kernel: capture the launch sequence in a hipGraph
+                                 and replay it when the same call is repeated */
+    int32_t regroup;          /* regrouped kernel schedule: 0 = default, 1 = cross-type
+                                 secondaries go through the photon/electron queues, 2 = they
+                                 stay on the lane's own stack (one lane transports a whole
+                                 history; the phases then only split new histories) */
 } mcd_opts;
 
 /* Output of a run.  dose and sigma (nx*ny*nz doubles each, Gy per source
  * history) and S, Q (raw tallies: sum over histories of the per-history
- * energy in a voxel and of its square, MeV and MeV^2) are caller-allocated
- * and optional (NULL to skip); they are device pointers when on_device != 0,
- * host pointers otherwise.  The scalars are filled on return. */
+ * energy in a voxel and of its square, MeV and MeV^2; Q only with the plain
+ * kernel) are caller-allocated and optional (NULL to skip); they are device
+ * pointers when on_device != 0, host pointers otherwise.  The scalars are
+ * filled on return. */
 typedef struct {
     double* dose;
     double* sigma;
@@ -174,6 +195,25 @@ int mcd_unload_phantom(mcd_ctx* ctx, int32_t phantom);
 int mcd_simulate(mcd_ctx* ctx, int32_t phantom, const mcd_source* src, uint64_t n_histories,
                  uint64_t seed, uint32_t request_key, const mcd_opts* opts, mcd_result* out,
                  void* hip_stream);
+
+/* One beam or beamlet of a batched call. */
+typedef struct {
+    mcd_source src;
+    uint64_t n_histories;
+    uint32_t request_key;
+    uint32_t reserved;
+    mcd_result* out;          /* per-item dose/sigma/S outputs and dmax, sigma_bar (eb and
+                                 counters are reported for the whole batch in `total`) */
+} mcd_batch_item;
+
+/* Runs many sources with uneven history counts on one phantom in one
+ * regrouped launch sequence (one hipGraph launch when opts->use_graph):
+ * their histories share the photon and electron phases, each item keeps its
+ * own tally.  Every item's result equals what mcd_simulate returns for it
+ * alone with the same seed and request key (up to FP64 summation order).
+ * n_items <= 4096; the sum of n_histories < 2^40. */
+int mcd_simulate_batch(mcd_ctx* ctx, int32_t phantom, const mcd_batch_item* items, int32_t n_items,
+                       uint64_t seed, const mcd_opts* opts, mcd_result* total, void* hip_stream);
 
 /* Status and error text. */
 const char* mcd_status_string(int status);

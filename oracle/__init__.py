@@ -70,11 +70,12 @@ def lib():
         L.orc_majorant.argtypes = [vp, sz, C.POINTER(Grid), u8p, f32p, dp]
         L.orc_simulate.argtypes = [vp, sz, C.POINTER(Grid), u8p, f32p, C.POINTER(Source),
                                    C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, dp, dp, dp,
-                                   C.POINTER(C.c_uint64), vp]
+                                   C.POINTER(C.c_uint64), vp, vp]
         L.orc_first_interaction.argtypes = [vp, sz, C.POINTER(Grid), u8p, f32p, C.POINTER(Source),
                                             C.c_uint64, C.c_uint32, C.c_uint32, dp, vp]
         L.orc_sample.argtypes = [vp, sz, C.c_int, C.c_double, C.c_uint64, C.c_uint32, dp]
         L.orc_finalize.argtypes = [C.POINTER(Grid), f32p, dp, dp, C.c_uint64, dp, dp, dp, dp]
+        L.orc_finalize_groups.argtypes = [C.POINTER(Grid), f32p, dp, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -149,7 +150,7 @@ def majorant(blob: bytes, ph) -> np.ndarray:
 
 
 def simulate(blob: bytes, ph, src, n: int, seed: int, key: int = 0, first: int = 0,
-             history: bool = False, S=None, Q=None) -> dict:
+             history: bool = False, S=None, Q=None, groups: bool = False) -> dict:
     """Runs histories [first, first + n); returns S, Q, balance, counters (and the
     per-history records if `history`)."""
     mat, rho = _phantom_arrays(ph)
@@ -159,18 +160,24 @@ def simulate(blob: bytes, ph, src, n: int, seed: int, key: int = 0, first: int =
     bal = np.zeros(NBAL)
     cnt = np.zeros(NCOUNT, dtype=np.uint64)
     hist = np.zeros(n, dtype=HISTORY_DTYPE) if history else None
+    Sb = np.zeros((16, nv)) if groups else None
     g = make_grid(ph)
     s = make_source(src)
     rc = lib().orc_simulate(blob, len(blob), C.byref(g), mat.ctypes.data, rho.ctypes.data,
                             C.byref(s), first, n, seed, key, _dp(S), _dp(Q), _dp(bal),
                             cnt.ctypes.data_as(C.POINTER(C.c_uint64)),
-                            hist.ctypes.data if hist is not None else None)
+                            hist.ctypes.data if hist is not None else None,
+                            Sb.ctypes.data if Sb is not None else None)
     if rc:
         raise ValueError(f"orc_simulate failed ({rc})")
     out = {"S": S, "Q": Q, "bal": dict(zip(BAL_NAMES, bal)), "bal_raw": bal,
            "cnt": dict(zip(COUNT_NAMES, (int(x) for x in cnt))), "cnt_raw": cnt, "n": n}
     if history:
         out["hist"] = hist
+    if groups:
+        out["Sb"] = Sb
+        out["nb"] = np.array([len(range(first + ((b - first) % 16), first + n, 16)) for b in range(16)],
+                             dtype=np.float64)
     return out
 
 
@@ -233,4 +240,18 @@ def finalize(ph, S, Q, n):
                           _dp(np.ascontiguousarray(Q)), n, _dp(dose), _dp(sigma),
                           C.byref(dmax), C.byref(sbar)):
         raise ValueError("orc_finalize rejected its input")
+    return dose, sigma, dmax.value, sbar.value
+
+
+def finalize_groups(ph, Sb, nb):
+    rho = np.ascontiguousarray(ph.rho, dtype=np.float32)
+    dose = np.zeros(ph.n_vox)
+    sigma = np.zeros(ph.n_vox)
+    dmax = C.c_double()
+    sbar = C.c_double()
+    g = make_grid(ph)
+    if lib().orc_finalize_groups(C.byref(g), rho.ctypes.data, _dp(np.ascontiguousarray(Sb)),
+                                 _dp(np.ascontiguousarray(nb, dtype=np.float64)), _dp(dose),
+                                 _dp(sigma), C.byref(dmax), C.byref(sbar)):
+        raise ValueError("orc_finalize_groups rejected its input")
     return dose, sigma, dmax.value, sbar.value

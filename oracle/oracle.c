@@ -406,6 +406,8 @@ typedef struct {
     uint32_t h;
     /* tally: per-history accumulation flushed at history end */
     double *S, *Q, *temp;
+    double* Sb;                        /* optional: 16 group tallies, history mod 16 */
+    size_t nv;
     unsigned char* touched;
     size_t *list, n_list, cap_list;
     double* bal;
@@ -448,6 +450,7 @@ static void flush_history(ctx* c)
         size_t v = c->list[i];
         c->S[v] += c->temp[v];
         c->Q[v] += c->temp[v] * c->temp[v];
+        if (c->Sb) c->Sb[(size_t)(c->h & 15u) * c->nv + v] += c->temp[v];
         c->temp[v] = 0.0;
         c->touched[v] = 0;
     }
@@ -819,7 +822,7 @@ static void build_cdf(const orc_source* src, double* cdf)
 int orc_simulate(const void* blob, size_t nbytes, const orc_grid* g, const uint8_t* mat,
                  const float* rho, const orc_source* src, uint64_t first, uint64_t n,
                  uint32_t seed, uint32_t request_key, double* S, double* Q, double* bal,
-                 uint64_t* cnt, orc_history* hist)
+                 uint64_t* cnt, orc_history* hist, double* Sb)
 {
     tables t;
     if (load_tables(blob, nbytes, &t)) return -1;
@@ -846,6 +849,8 @@ int orc_simulate(const void* blob, size_t nbytes, const orc_grid* g, const uint8
     c.k1 = request_key;
     c.S = S;
     c.Q = Q;
+    c.Sb = Sb;
+    c.nv = nv;
     c.bal = bal;
     c.cnt = cnt;
     c.temp = (double*)calloc(nv, sizeof(double));
@@ -1038,6 +1043,54 @@ int orc_finalize(const orc_grid* g, const float* rho, const double* S, const dou
             ++cntv;
         }
     }
+    if (dmax) *dmax = mx;
+    if (sigma_bar) *sigma_bar = cntv ? acc / (double)cntv : 0.0;
+    return 0;
+}
+
+/* Group ("batch") statistics: the histories are split into 16 groups by
+ * history mod 16 with nb[b] histories and group tallies Sb[b][v].  The dose
+ * comes from S = sum_b Sb; the per-history variance is estimated from the
+ * spread of the group means m_b = Sb/nb[b] around m = S/N,
+ *     s^2 = sum_b nb[b] (m_b - m)^2 / (B' - 1),  sigma_mean^2 = s^2 / N,
+ * with B' the number of non-empty groups. */
+int orc_finalize_groups(const orc_grid* g, const float* rho, const double* Sb, const double* nb,
+                        double* dose, double* sigma, double* dmax, double* sigma_bar)
+{
+    if (!g || !rho || !Sb || !nb || !dose || !sigma) return -1;
+    size_t nv = (size_t)g->nx * g->ny * g->nz;
+    double vol = g->dx * g->dy * g->dz;
+    double N = 0.0;
+    int groups = 0;
+    for (int b = 0; b < 16; ++b) {
+        N += nb[b];
+        if (nb[b] > 0.0) ++groups;
+    }
+    if (!(N > 0.0)) return -1;
+    double mx = 0.0;
+    for (size_t v = 0; v < nv; ++v) {
+        double S = 0.0;
+        for (int b = 0; b < 16; ++b) S += Sb[(size_t)b * nv + v];
+        double m = S / N;
+        double ss = 0.0;
+        for (int b = 0; b < 16; ++b) {
+            if (nb[b] <= 0.0) continue;
+            double dm = Sb[(size_t)b * nv + v] / nb[b] - m;
+            ss += nb[b] * dm * dm;
+        }
+        double var = groups > 1 ? ss / (groups - 1) / N : 0.0;
+        double scale = MEV_PER_G_TO_GY / ((double)rho[v] * vol);
+        dose[v] = m * scale;
+        sigma[v] = sqrt(var) * scale;
+        if (dose[v] > mx) mx = dose[v];
+    }
+    double acc = 0.0;
+    size_t cntv = 0;
+    for (size_t v = 0; v < nv; ++v)
+        if (dose[v] > 0.5 * mx) {
+            acc += sigma[v] / dose[v];
+            ++cntv;
+        }
     if (dmax) *dmax = mx;
     if (sigma_bar) *sigma_bar = cntv ? acc / (double)cntv : 0.0;
     return 0;

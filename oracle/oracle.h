@@ -86,11 +86,13 @@ int orc_majorant(const void* blob, size_t nbytes, const orc_grid* g, const uint8
 
 /* Transport histories [first, first + n) and accumulate the dose tallies
  * S[v] += sum_h e_{h,v}, Q[v] += sum_h e_{h,v}^2 (MeV, MeV^2).  `bal` has
- * ORC_NBAL entries, `cnt` ORC_NCOUNT; `hist` (n entries) may be NULL. */
+ * ORC_NBAL entries, `cnt` ORC_NCOUNT; `hist` (n entries) may be NULL; `Sb`
+ * (16 x nv, or NULL) accumulates the group tallies, history h into group
+ * h mod 16. */
 int orc_simulate(const void* blob, size_t nbytes, const orc_grid* g, const uint8_t* mat,
                  const float* rho, const orc_source* src, uint64_t first, uint64_t n,
                  uint32_t seed, uint32_t request_key, double* S, double* Q, double* bal,
-                 uint64_t* cnt, orc_history* hist);
+                 uint64_t* cnt, orc_history* hist, double* Sb);
 
 /* Depth z of the primary photon's first real interaction for each history of a
  * photon source (+inf when it escapes first, NaN when it misses the phantom),
@@ -116,6 +118,11 @@ int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n,
  * source history, Dmax and sigma-bar (mean sigma/D over voxels with D > Dmax/2). */
 int orc_finalize(const orc_grid* g, const float* rho, const double* S, const double* Q,
                  uint64_t n, double* dose, double* sigma, double* dmax, double* sigma_bar);
+
+/* Finalisation with group statistics: dose from the summed group tallies and
+ * sigma from the spread of the 16 group means (nb[b] histories in group b). */
+int orc_finalize_groups(const orc_grid* g, const float* rho, const double* Sb, const double* nb,
+                        double* dose, double* sigma, double* dmax, double* sigma_bar);
 
 #ifdef __cplusplus
 }

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmcdose.so")
-SOURCES = ("kernels.hip", "runtime.hip")
+SOURCES = ("k_plain.hip", "k_regroup.hip", "k_final.hip", "runtime.hip", "sched.hip", "serve.hip")
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
@@ -24,7 +24,8 @@ HIPCC_FLAGS = [
 
 
 # Production (non-diagnostic) transport kernels: checked for private scratch.
-HOT_KERNELS = ("_ZN3mcd11k_transportILb0EEEvNS_7KParamsE",)
+HOT_KERNELS = ("_ZN3mcd7k_plainILb0EEEvNS_6KPlainE", "_ZN3mcd7k_phaseILb0ELb1EEEvNS_6KPhaseE",
+               "_ZN3mcd7k_phaseILb0ELb0EEEvNS_6KPhaseE")
 
 
 def resource_usage(remarks: str) -> dict:

@@ -11,7 +11,8 @@ constexpr int kNE = 512;          // energy nodes of every table
 constexpr int kMaxMat = 8;        // materials per table set on the device
 constexpr int kCounters = 32;
 constexpr int kBal = 6;           // e_src, e_csda, e_local, e_esc, e_miss, track_e
-constexpr int kStackRec = 48;     // bytes per stacked particle
+constexpr int kRec = 48;          // bytes per stacked or queued particle
+constexpr int kBatches = 16;      // sub-tallies of the batch-statistics tally (power of two)
 
 // Device-side tables of one material set (FP32, converted from the FP64 blob).
 //   phot[m*512 + i] = (mu_C/rho, mu_pe/rho, mu_pp/rho, 0)   cm^2/g
@@ -28,7 +29,7 @@ struct DevTables {
     float e_abs_e, e_abs_g, w_cc, w_cr, kappa_step, f_e, a_hinge;
 };
 
-// Source descriptor as the kernel sees it.
+// Source descriptor as the kernels see it.
 struct DevSource {
     int particle, energy_kind, beam_kind, n_bins;
     float e0;
@@ -39,13 +40,19 @@ struct DevSource {
     double extra;           // 2 m c^2 for positron primaries, else 0
 };
 
-// Everything one transport launch needs.
-struct KParams {
+// Tables and phantom of a launch.
+struct KGeom {
     DevTables t;
     const float* maj;        // [512] majorant attenuation of the phantom, 1/cm
     const uint2* vox;        // per voxel: (float bits of rho, material index)
     int nx, ny, nz;
     float dx, dy, dz, x0, y0, z0, x1, y1, z1, idx, idy, idz;
+};
+
+// Plain per-history kernel: one lane follows one history at a time with an
+// exact history-by-history local counter.
+struct KPlain {
+    KGeom g;
     DevSource src;
     uint32_t seed, key;
     uint32_t first, n;       // history range [first, first + n)
@@ -54,25 +61,88 @@ struct KParams {
     double* bal;             // [kBal]
     unsigned long long* cnt; // [kCounters]
     int* err;                // 0 ok, else an mcd_status
-    unsigned long long* next; // work counter: next history offset
+    unsigned long long* next;// work counter: next history offset
     char* scratch;           // per-lane stack and local counter
     int stack_depth;
     int slots;               // local counter slots, power of two
-    int lockstep;            // 1: all lanes of a wave run the same history
     size_t lane_bytes;
     void* hist;              // mcd_history_record[n] or null
+    int lockstep;            // 1: all lanes of a wave run the same history
 };
 
-size_t lane_scratch_bytes(int stack_depth, int slots);
+// One request of a regrouped launch (device copy).
+struct ReqDev {
+    DevSource src;
+    uint32_t seed, key;
+    uint32_t first, n;       // history range
+    uint64_t lo;             // index of its first history in the launch's work list
+    void* tally;             // kBatches sub-tallies of nv voxels (double or float)
+    void* hist;              // mcd_history_record[n] or null (diagnostics)
+};
 
-// Launchers (kernels.hip).
-hipError_t launch_transport(const KParams& p, int blocks, int threads, bool diag, hipStream_t s);
+// Queue control words: count (particles appended), head (particles taken).
+struct QCtl {
+    unsigned int count, head, pad0, pad1;
+};
+
+// One phase of a regrouped cycle: the photon phase takes photons queued by the
+// previous electron phase plus new histories; the electron phase takes the
+// electrons the photon phase queued.  Cross-type secondaries go to the other
+// type's queue (or, when it is full, stay on the lane's own stack).
+struct KPhase {
+    KGeom g;
+    const ReqDev* req;
+    int n_req;
+    int tally_fp32;
+    uint64_t total;          // histories in the launch
+    uint64_t chunk;          // new histories per cycle
+    uint32_t cycle;
+    unsigned int* claim;     // per-cycle claim counters
+    const char* q_in;        // queue consumed by this phase
+    QCtl* q_in_ctl;
+    char* q_out;             // queue of the other particle type, appended to
+    QCtl* q_out_ctl;
+    QCtl* q_reset_ctl;       // control block zeroed at the start of this phase
+    unsigned int q_cap;      // capacity of every queue buffer (particles)
+    int use_queues;          // 0: cross-type secondaries stay on the lane stack
+    int64_t nv;
+    double* bal;
+    unsigned long long* cnt;
+    int* err;
+    char* scratch;           // per-lane particle stacks
+    int stack_depth;
+    size_t lane_bytes;
+};
+
+size_t plain_lane_bytes(int stack_depth, int slots);
+size_t phase_lane_bytes(int stack_depth);
+int transport_lds_bytes(int n_mat);
+
+// Launchers.
+hipError_t launch_plain(const KPlain& p, int blocks, int threads, bool diag, hipStream_t s);
+hipError_t launch_phase(const KPhase& p, bool photons, int blocks, int threads, bool diag,
+                        hipStream_t s);
 hipError_t launch_finalize(const double* S, const double* Q, const uint2* vox, int64_t nv,
                            double vol, uint64_t n, double* dose, double* sigma, double* red,
                            hipStream_t s);
+// Batch-statistics finalisation of n_req tallies (kBatches sub-tallies each).
+struct FinalReq {
+    const void* tally;
+    double* S;               // sum of the sub-tallies, or null
+    double* dose;
+    double* sigma;
+    double* red;             // [3]: Dmax bits, sum sigma/D, count
+    double nb[kBatches];     // histories per sub-tally
+};
+hipError_t launch_finalize_batches(const FinalReq* reqs, int n_req, const uint2* vox,
+                                   int64_t nv, double vol, int fp32, hipStream_t s);
 hipError_t launch_clear_lane_keys(char* scratch, size_t lanes, size_t lane_bytes, int stack_depth,
                                   int slots, hipStream_t s);
 hipError_t launch_fill_u32(void* p, size_t n_words, uint32_t v, hipStream_t s);
-int transport_lds_bytes(int n_mat);
+// Sets the dynamic-LDS limit of the transport kernels (once, before any launch
+// or graph capture).
+hipError_t init_kernels(int max_lds);
+hipError_t init_plain_kernels(int max_lds);
+hipError_t init_phase_kernels(int max_lds);
 
 }  // namespace mcd

@@ -1,0 +1,267 @@
+// Regrouped transport: particles are sorted by type into queues so that every
+// wave runs one kind of step (photon flights or electron segments) and the
+// wavefront does not serialise the two code paths.
+//
+// A cycle is a photon phase followed by an electron phase.  The photon phase
+// transports the photons queued by the previous electron phase and up to
+// `chunk` new histories (photon primaries in place; electron and positron
+// primaries are queued); electrons and positrons it creates are queued for the
+// electron phase.  The electron phase transports them; the photons it creates
+// (bremsstrahlung, annihilation) are queued for the next photon phase.
+// Same-type secondaries stay on the lane's own stack, and so does a
+// cross-type secondary when the other queue is full, so no particle is lost
+// and the result does not depend on the queue capacity.  Every lane loops
+// until its phase has no work left; the host (or a captured graph) repeats
+// cycles until all histories are claimed and the queues are empty.
+//
+// Histories of several requests (beams, beamlets, served requests) share a
+// launch: each particle carries its request slot, which selects the Philox key
+// and the request's tally.  The tally is batch-statistical: history h adds to
+// sub-tally h mod 16, and the uncertainty comes from the spread of the 16
+// sub-tally means.  Consecutive deposits of a particle into one voxel are
+// summed in registers and added with one atomic per voxel visit.
+#include "transport.h"
+
+namespace mcd {
+
+template <bool DIAG, bool PHOTONS>
+struct PhaseLane : Transport<PhaseLane<DIAG, PHOTONS>, DIAG> {
+    const KPhase& p;
+    char* stack;
+    int sp;
+    int cur_v;
+    float cur_e;
+    // request context of the particle in flight
+    int slot;
+    void* tally;
+    mcd_history_record* hist;
+    uint32_t first;
+    // per-particle diagnostics
+    double p_edep, p_track;
+
+    DEV PhaseLane(const KPhase& pp, char* base) : Transport<PhaseLane<DIAG, PHOTONS>, DIAG>(pp.g),
+                                                   p(pp), stack(base), sp(0), cur_v(-1), cur_e(0.f),
+                                                   slot(-1), tally(nullptr), hist(nullptr), first(0),
+                                                   p_edep(0.0), p_track(0.0) {}
+
+    DEV void fail(int status)
+    {
+        this->failed = 1;
+        atomicCAS(p.err, 0, status);
+    }
+
+    DEV void use_request(uint32_t s)
+    {
+        if ((int)s == slot) return;
+        const ReqDev& r = p.req[s];
+        slot = (int)s;
+        this->env.seed = r.seed;
+        this->env.key = r.key;
+        tally = r.tally;
+        hist = (mcd_history_record*)r.hist;
+        first = r.first;
+    }
+
+    DEV void flush_visit(const Part& q)
+    {
+        if (cur_v < 0) return;
+        const size_t idx = (size_t)(q.h & (kBatches - 1)) * (size_t)p.nv + (size_t)cur_v;
+        if (p.tally_fp32) unsafeAtomicAdd((float*)tally + idx, cur_e);
+        else unsafeAtomicAdd((double*)tally + idx, (double)cur_e);
+        if (DIAG) ++this->c[MCD_C_FLUSHES];
+        cur_v = -1;
+    }
+
+    DEV void deposit(const Part& q, int v, float e)
+    {
+        if (e == 0.f) return;
+        if (DIAG) p_edep += (double)e;
+        if (v == cur_v) {
+            cur_e += e;
+        } else {
+            flush_visit(q);
+            cur_v = v;
+            cur_e = e;
+        }
+    }
+
+    DEV void flush_particle(const Part& q)
+    {
+        flush_visit(q);
+        if (DIAG && hist && p_edep != 0.0) unsafeAtomicAdd(&hist[q.h - first].edep, p_edep);
+        p_edep = 0.0;
+    }
+
+    DEV void add_track(const Part&, float l) { if (DIAG) p_track += (double)l; }
+
+    DEV void escaped(const Part& q)
+    {
+        if (DIAG && hist) atomicMax(&hist[q.h - first].escaped, 1u);
+    }
+
+    DEV void particle_done(const Part& q, uint64_t ph)
+    {
+        flush_visit(q);
+        if (DIAG && hist) {
+            mcd_history_record* r = &hist[q.h - first];
+            if (p_edep != 0.0) unsafeAtomicAdd(&r->edep, p_edep);
+            if (p_track != 0.0) unsafeAtomicAdd(&r->track_e, p_track);
+            atomicAdd((unsigned long long*)&r->hash, (unsigned long long)ph);
+            atomicAdd(&r->n_particles, 1u);
+        }
+        p_edep = p_track = 0.0;
+    }
+
+    DEV void push_stack(const Part& s)
+    {
+        if (sp >= p.stack_depth) {
+            fail(MCD_E_OVERFLOW);
+            return;
+        }
+        store_rec(stack + (size_t)sp * kRec, s);
+        ++sp;
+        if (DIAG && (uint32_t)sp > this->c[MCD_C_MAX_STACK]) this->c[MCD_C_MAX_STACK] = (uint32_t)sp;
+    }
+
+    DEV void spawn(const Part& s)
+    {
+        const bool cross = PHOTONS ? s.type != PHOTON : s.type == PHOTON;
+        if (cross && p.use_queues) {
+            const unsigned int i = atomicAdd(&p.q_out_ctl->count, 1u);
+            if (i < p.q_cap) {
+                store_rec(p.q_out + (size_t)i * kRec, s);
+                return;
+            }
+        }
+        push_stack(s);
+    }
+
+    // Starts transport of a particle read from a stack or queue.
+    DEV bool begin(Part& q)
+    {
+        if (q.type < PHOTON || q.type > POSITRON || (int)q.slot >= p.n_req) {
+            fail(MCD_E_DEVICE);
+            return false;
+        }
+        use_request(q.slot);
+        this->start_particle(q);
+        return true;
+    }
+
+    // Claims the next new history of this cycle.  Returns false when none is left.
+    DEV bool claim(Part& q)
+    {
+        const unsigned int j = atomicAdd(&p.claim[p.cycle], 1u);
+        const uint64_t gi = (uint64_t)p.cycle * p.chunk + j;
+        if ((uint64_t)j >= p.chunk || gi >= p.total) return false;
+        int lo = 0, hi = p.n_req - 1;          // last request whose first index <= gi
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (p.req[mid].lo <= gi) lo = mid; else hi = mid - 1;
+        }
+        const ReqDev& r = p.req[lo];
+        use_request((uint32_t)lo);
+        q.slot = (uint32_t)lo;
+        q.h = r.first + (uint32_t)(gi - r.lo);
+        this->start_history(q, r.src, r.src.edges, r.src.cdf);
+        if (q.type == DEAD) {
+            flush_particle(q);
+        } else if (q.type == PHOTON) {
+            this->start_particle(q);
+        } else {
+            spawn(q);               // electron or positron primary: to the electron phase
+            q.type = DEAD;
+        }
+        return true;
+    }
+};
+
+template <bool DIAG, bool PHOTONS>
+__global__ __launch_bounds__(512) void k_phase(KPhase p)
+{
+    extern __shared__ float4 lds[];
+    Env env;
+    float* extra;
+    stage_tables(p.g, lds, env, &extra);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        p.q_reset_ctl->count = 0u;
+        p.q_reset_ctl->head = 0u;
+    }
+    __syncthreads();
+
+    const size_t lane_id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    PhaseLane<DIAG, PHOTONS> L(p, p.scratch + lane_id * p.lane_bytes);
+    L.env = env;
+    L.init_base();
+    const unsigned int n_in = min(p.q_in_ctl->count, p.q_cap);
+    bool more_new = PHOTONS;
+    Part q;
+    q.type = DEAD;
+    for (;;) {
+        if (q.type == DEAD) {
+            if (L.sp > 0) {
+                --L.sp;
+                load_rec(L.stack + (size_t)L.sp * kRec, q);
+                if (!L.begin(q)) break;
+            } else {
+                bool got = false;
+                if (n_in) {
+                    const unsigned int i = atomicAdd(&p.q_in_ctl->head, 1u);
+                    if (i < n_in) {
+                        load_rec(p.q_in + (size_t)i * kRec, q);
+                        if (!L.begin(q)) break;
+                        got = true;
+                    }
+                }
+                if (!got && more_new) {
+                    more_new = L.claim(q);
+                    got = more_new;
+                }
+                if (!got || L.failed) break;
+            }
+            continue;
+        }
+        L.step(q);
+        if (L.failed) break;
+    }
+    L.reduce_out(p.bal, p.cnt);
+}
+
+size_t phase_lane_bytes(int stack_depth)
+{
+    size_t b = (size_t)stack_depth * kRec;
+    return (b + 255) & ~(size_t)255;
+}
+
+hipError_t launch_phase(const KPhase& p, bool photons, int blocks, int threads, bool diag,
+                        hipStream_t s)
+{
+    const size_t lds = transport_lds_bytes(p.g.t.n_mat);
+    if (photons) {
+        if (diag) hipLaunchKernelGGL((k_phase<true, true>), dim3(blocks), dim3(threads), lds, s, p);
+        else hipLaunchKernelGGL((k_phase<false, true>), dim3(blocks), dim3(threads), lds, s, p);
+    } else {
+        if (diag) hipLaunchKernelGGL((k_phase<true, false>), dim3(blocks), dim3(threads), lds, s, p);
+        else hipLaunchKernelGGL((k_phase<false, false>), dim3(blocks), dim3(threads), lds, s, p);
+    }
+    return hipGetLastError();
+}
+
+hipError_t init_phase_kernels(int max_lds)
+{
+    const void* fns[4] = {(const void*)k_phase<true, true>, (const void*)k_phase<false, true>,
+                          (const void*)k_phase<true, false>, (const void*)k_phase<false, false>};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t init_kernels(int max_lds)
+{
+    hipError_t e = init_plain_kernels(max_lds);
+    return e == hipSuccess ? init_phase_kernels(max_lds) : e;
+}
+
+}  // namespace mcd

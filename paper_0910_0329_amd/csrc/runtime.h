@@ -3,9 +3,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <condition_variable>
 #include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "engine.h"
@@ -16,10 +21,13 @@ namespace mcd {
 constexpr int kDefaultBlock = 512;
 constexpr int kDefaultDepth = 64;
 constexpr int kDefaultSlots = 512;
+constexpr int kDefaultChunkPerLane = 16;
 constexpr int kLdsPerCu = 160 * 1024;
+constexpr int kTailCycles = 8;      // cycles scheduled after the last new history
+constexpr int kMaxBatch = 4096;
 
 // Small per-run device block: energy balance, counters, error flag, work
-// counter and finalisation reductions.
+// counter and finalisation reductions of the plain kernel.
 constexpr size_t kOffBal = 0;       // kBal doubles
 constexpr size_t kOffCnt = 64;      // kCounters u64
 constexpr size_t kOffErr = 320;     // int
@@ -47,7 +55,45 @@ struct PhantomRec {
     bool live = false;
 };
 
+// Device buffers of one regrouped launch sequence (queues, requests, tallies).
+struct RegroupBufs {
+    char* queues = nullptr;          // 4 buffers of cap records: Qg[0], Qg[1], Qe[0], Qe[1]
+    unsigned int cap = 0;
+    QCtl* ctl = nullptr;             // 4 control blocks
+    unsigned int* claim = nullptr;   // per-cycle claim counters
+    int claim_cap = 0;
+    ReqDev* req = nullptr;
+    int req_cap = 0;
+    FinalReq* fin = nullptr;
+    double* red = nullptr;           // 3 doubles per request
+    void* tally = nullptr;           // n_req * kBatches * nv accumulators
+    size_t tally_bytes = 0;
+    double* dose = nullptr;          // staging: n_req * nv
+    double* sigma = nullptr;
+    size_t stage_bytes = 0;
+    char* scratch = nullptr;         // lane stacks
+    size_t scratch_bytes = 0;
+};
+
+// A prepared regrouped run: everything the kernels and the finaliser need.
+struct RegroupPlan {
+    int phantom = -1;
+    int n_req = 0;
+    uint64_t total = 0, chunk = 0;
+    int cycles = 0;                  // scheduled cycles
+    int blocks = 0, threads = 0;
+    int depth = 0;
+    int fp32 = 0;
+    bool diag = false;
+    bool use_queues = false;
+    std::vector<ReqDev> req;
+    std::vector<FinalReq> fin;
+    std::vector<double> nb;          // n_req * kBatches histories per sub-tally
+};
+
 }  // namespace mcd
+
+struct mcd_server;
 
 struct mcd_ctx {
     int device = 0;
@@ -55,18 +101,17 @@ struct mcd_ctx {
     int max_lds = 0;     // dynamic LDS bytes a workgroup may use
     hipStream_t stream = nullptr;
     uint64_t budget = 0, used = 0;
-    std::mutex mu;        // tables / phantoms vectors
+    std::mutex mu;        // tables / phantoms vectors, allocation accounting
     std::mutex run_mu;    // one blocking run at a time
+    std::mutex mu_alloc;  // budget accounting
     std::vector<mcd::TableSet> tables;
     std::vector<mcd::PhantomRec> phantoms;
 
-    // lane scratch (particle stacks and local counters)
+    // plain kernel: lane scratch (stacks and local counters) and tallies
     char* scratch = nullptr;
     size_t scratch_bytes = 0, scratch_lanes = 0, lane_bytes = 0;
     int stack_depth = 0, slot_count = 0;
     bool keys_clean = false;
-
-    // tallies of the blocking path and host-output staging
     double* S = nullptr;
     double* Q = nullptr;
     int64_t tally_cap = 0;
@@ -78,18 +123,43 @@ struct mcd_ctx {
     unsigned char* small = nullptr;
     hipEvent_t ev[4] = {};
 
+    // regrouped kernel
+    mcd::RegroupBufs rb;
+    int rg_owner = -1;                // phantom of the accumulated regrouped tally
+    std::vector<double> rg_nb;        // accumulated histories per sub-tally
+    int rg_fp32 = -1;
+    // graph cache for repeated batched calls
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<unsigned char> graph_key;
+
+    // serving
+    mcd_server* server = nullptr;
+
     std::string last_error;
 
     int fail(int status, const std::string& msg);
     int hip_fail(hipError_t e, const char* what);
     int alloc(void** p, size_t bytes, const char* what);
     void release(void* p, size_t bytes);
+    int grow(void** p, size_t* have, size_t need, const char* what);
     int validate_source(const mcd_source* s, mcd::DevSource* d);
     int ensure_scratch(size_t lanes, int depth, int slots, hipStream_t s);
     int ensure_tallies(int64_t nv, hipStream_t s);
     int ensure_stage(int64_t nv, hipStream_t s);
     int launch_shape(const mcd_opts* o, int n_mat, int* blocks, int* threads);
-    void fill_params(mcd::KParams& p, const mcd::PhantomRec& ph, const mcd::DevSource& ds,
-                     uint64_t seed, uint32_t key, uint64_t first, uint64_t n);
-    void shutdown_serving() {}
+    void fill_geom(mcd::KGeom& g, const mcd::PhantomRec& ph);
+    int simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n, uint64_t seed,
+                       uint32_t key, const mcd_opts* opts, mcd_result* out, hipStream_t s);
+    // regrouped engine
+    int plan_regroup(int32_t phantom, const mcd_source* const* srcs, const uint64_t* ns,
+                     const uint32_t* keys, int n_req, uint64_t seed, const mcd_opts* opts,
+                     bool keep_tally, mcd::RegroupPlan& plan);
+    int enqueue_regroup(const mcd::RegroupPlan& plan, bool clear_tally, hipStream_t s);
+    int enqueue_cycles(const mcd::RegroupPlan& plan, int c0, int c1, hipStream_t s);
+    int finish_regroup(mcd::RegroupPlan& plan, hipStream_t s, int* cycles_run);
+    int collect_regroup(const mcd::RegroupPlan& plan, mcd_result* const* outs, mcd_result* total,
+                        hipStream_t s);
+    void release_graph();
+    void shutdown_serving();
 };

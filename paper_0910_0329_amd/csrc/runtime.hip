@@ -55,6 +55,7 @@ int mcd_ctx::alloc(void** p, size_t bytes, const char* what)
 {
     *p = nullptr;
     if (bytes == 0) return MCD_OK;
+    std::lock_guard<std::mutex> g(mu_alloc);
     if (used + bytes > budget)
         return fail(MCD_E_NOMEM, std::string(what) + ": allocation of " + std::to_string(bytes) +
                                      " bytes exceeds the HBM budget");
@@ -70,8 +71,24 @@ int mcd_ctx::alloc(void** p, size_t bytes, const char* what)
 void mcd_ctx::release(void* p, size_t bytes)
 {
     if (!p) return;
+    std::lock_guard<std::mutex> g(mu_alloc);
     (void)hipFree(p);
     used -= std::min(used, (uint64_t)bytes);
+}
+
+// Grows a device buffer to at least `need` bytes (contents are not kept).
+int mcd_ctx::grow(void** p, size_t* have, size_t need, const char* what)
+{
+    if (*p && *have >= need) return MCD_OK;
+    if (*p) {
+        (void)hipDeviceSynchronize();
+        release(*p, *have);
+        *p = nullptr;
+        *have = 0;
+    }
+    int rc = alloc(p, need, what);
+    if (rc == MCD_OK) *have = need;
+    return rc;
 }
 
 // ------------------------------------------------------------- create/destroy
@@ -109,6 +126,10 @@ int mcd_create(int device, uint64_t hbm_budget_bytes, mcd_ctx** out)
         return MCD_E_NOMEM;
     }
     for (auto& e : c->ev) (void)hipEventCreate(&e);
+    if (init_kernels(c->max_lds) != hipSuccess) {
+        mcd_destroy(c);
+        return MCD_E_DEVICE;
+    }
     *out = c;
     return MCD_OK;
 }
@@ -135,6 +156,18 @@ int mcd_destroy(mcd_ctx* c)
     c->release(c->dose, c->stage_cap * sizeof(double));
     c->release(c->sigma, c->stage_cap * sizeof(double));
     c->release(c->small, kSmallBytes);
+    c->release_graph();
+    RegroupBufs& rb = c->rb;
+    c->release(rb.queues, (size_t)4 * rb.cap * kRec);
+    c->release(rb.ctl, 4 * sizeof(QCtl));
+    c->release(rb.claim, (size_t)rb.claim_cap * 4);
+    c->release(rb.req, (size_t)rb.req_cap * sizeof(ReqDev));
+    c->release(rb.fin, (size_t)rb.req_cap * sizeof(FinalReq));
+    c->release(rb.red, (size_t)rb.req_cap * 3 * sizeof(double));
+    c->release(rb.tally, rb.tally_bytes);
+    c->release(rb.dose, rb.stage_bytes);
+    c->release(rb.sigma, rb.stage_bytes);
+    c->release(rb.scratch, rb.scratch_bytes);
     for (auto& e : c->ev) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(c->stream);
     delete c;
@@ -406,7 +439,7 @@ int mcd_ctx::validate_source(const mcd_source* s, DevSource* d)
 
 int mcd_ctx::ensure_scratch(size_t lanes, int depth, int slots, hipStream_t s)
 {
-    const size_t lb = lane_scratch_bytes(depth, slots);
+    const size_t lb = plain_lane_bytes(depth, slots);
     if (scratch && lanes <= scratch_lanes && lb == lane_bytes && depth == stack_depth &&
         slots == slot_count && keys_clean)
         return MCD_OK;
@@ -473,173 +506,3 @@ int mcd_ctx::ensure_stage(int64_t nv, hipStream_t s)
     return MCD_OK;
 }
 
-void mcd_ctx::fill_params(KParams& p, const PhantomRec& ph, const DevSource& ds, uint64_t seed,
-                          uint32_t key, uint64_t first, uint64_t n)
-{
-    std::memset(&p, 0, sizeof p);
-    p.t = tables[ph.tables].dev;
-    p.maj = ph.maj;
-    p.vox = ph.vox;
-    p.nx = ph.g.nx;
-    p.ny = ph.g.ny;
-    p.nz = ph.g.nz;
-    p.dx = (float)ph.g.dx;
-    p.dy = (float)ph.g.dy;
-    p.dz = (float)ph.g.dz;
-    p.x0 = (float)ph.g.x0;
-    p.y0 = (float)ph.g.y0;
-    p.z0 = (float)ph.g.z0;
-    p.x1 = (float)(ph.g.x0 + ph.g.nx * ph.g.dx);
-    p.y1 = (float)(ph.g.y0 + ph.g.ny * ph.g.dy);
-    p.z1 = (float)(ph.g.z0 + ph.g.nz * ph.g.dz);
-    p.idx = (float)(1.0 / ph.g.dx);
-    p.idy = (float)(1.0 / ph.g.dy);
-    p.idz = (float)(1.0 / ph.g.dz);
-    p.src = ds;
-    p.seed = (uint32_t)seed;
-    p.key = key;
-    p.first = (uint32_t)first;
-    p.n = (uint32_t)n;
-}
-
-int mcd_ctx::launch_shape(const mcd_opts* o, int n_mat, int* blocks, int* threads)
-{
-    int t = o && o->block_size ? o->block_size : kDefaultBlock;
-    if (t < 64 || t > 512 || (t & 63)) return fail(MCD_E_INVAL, "opts: block_size must be a multiple of 64 in [64, 512]");
-    int b = o && o->grid_blocks ? o->grid_blocks : 0;
-    if (b < 0) return fail(MCD_E_INVAL, "opts: grid_blocks must be >= 0");
-    const int lds = transport_lds_bytes(n_mat);
-    if (lds > max_lds)
-        return fail(MCD_E_INVAL, "tables need " + std::to_string(lds) + " bytes of LDS per workgroup; the device allows " +
-                                     std::to_string(max_lds));
-    if (b == 0) {
-        const int per_cu = std::max(1, std::min(kLdsPerCu / lds, 2048 / t));
-        b = cu_count * per_cu;
-    }
-    *blocks = b;
-    *threads = t;
-    return MCD_OK;
-}
-
-int mcd_simulate(mcd_ctx* c, int32_t phantom, const mcd_source* src, uint64_t n_histories,
-                 uint64_t seed, uint32_t request_key, const mcd_opts* opts, mcd_result* out,
-                 void* hip_stream)
-{
-    if (!c || !out) return MCD_E_INVAL;
-    std::lock_guard<std::mutex> run_lock(c->run_mu);
-    if (phantom < 0 || phantom >= (int32_t)c->phantoms.size() || !c->phantoms[phantom].live)
-        return c->fail(MCD_E_NOTFOUND, "unknown phantom handle");
-    const PhantomRec& ph = c->phantoms[phantom];
-    const uint64_t first = opts ? opts->first_history : 0;
-    if (n_histories == 0 || n_histories >= ((uint64_t)1 << 32) || seed >= ((uint64_t)1 << 32) ||
-        first >= ((uint64_t)1 << 32) || first + n_histories > ((uint64_t)1 << 32))
-        return c->fail(MCD_E_INVAL, "need 1 <= n_histories < 2^32, seed < 2^32, first + n <= 2^32");
-    if (n_histories < 2 && (out->dose || out->sigma))
-        return c->fail(MCD_E_INVAL, "an uncertainty needs at least 2 histories");
-    DevSource ds;
-    int rc = c->validate_source(src, &ds);
-    if (rc) return rc;
-    const int depth = opts && opts->stack_depth ? opts->stack_depth : kDefaultDepth;
-    const int slots = opts && opts->tally_slots ? opts->tally_slots : kDefaultSlots;
-    if (depth < 4 || depth > 4096) return c->fail(MCD_E_INVAL, "opts: stack_depth in [4, 4096]");
-    if (slots < 16 || slots > 32768 || (slots & (slots - 1)))
-        return c->fail(MCD_E_INVAL, "opts: tally_slots must be a power of two in [16, 32768]");
-    int blocks, threads;
-    rc = c->launch_shape(opts, c->tables[ph.tables].n_mat, &blocks, &threads);
-    if (rc) return rc;
-    const bool diag = opts && opts->diagnostics;
-    const bool accumulate = opts && opts->accumulate;
-    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
-    (void)hipSetDevice(c->device);
-
-    if ((rc = c->ensure_scratch((size_t)blocks * threads, depth, slots, s))) return rc;
-    if ((rc = c->ensure_tallies(ph.nv, s))) return rc;
-    const bool want_final = out->dose || out->sigma;
-    if (want_final && (!out->on_device || !out->dose || !out->sigma))
-        if ((rc = c->ensure_stage(ph.nv, s))) return rc;
-    if (accumulate && c->tally_owner != phantom)
-        return c->fail(MCD_E_INVAL, "opts.accumulate: the previous run used another phantom");
-
-    KParams p;
-    c->fill_params(p, ph, ds, seed, request_key, first, n_histories);
-    p.S = c->S;
-    p.Q = c->Q;
-    p.bal = (double*)(c->small + kOffBal);
-    p.cnt = (unsigned long long*)(c->small + kOffCnt);
-    p.err = (int*)(c->small + kOffErr);
-    p.next = (unsigned long long*)(c->small + kOffNext);
-    p.scratch = c->scratch;
-    p.stack_depth = depth;
-    p.slots = slots;
-    p.lane_bytes = c->lane_bytes;
-    p.hist = diag && opts ? opts->history_records : nullptr;
-    p.lockstep = opts && opts->lockstep ? 1 : 0;
-    if (p.lockstep && (threads & 63)) return c->fail(MCD_E_INVAL, "lockstep needs whole waves");
-    if (p.hist && !diag) return c->fail(MCD_E_INVAL, "history records need diagnostics");
-    double* red = (double*)(c->small + kOffRed);
-
-    hipError_t e = hipEventRecord(c->ev[0], s);
-    if (e == hipSuccess && !accumulate) {
-        e = launch_fill_u32(c->S, (size_t)ph.nv * 2, 0u, s);
-        if (e == hipSuccess) e = launch_fill_u32(c->Q, (size_t)ph.nv * 2, 0u, s);
-    }
-    if (e == hipSuccess) e = launch_fill_u32(c->small, kSmallBytes / 4, 0u, s);
-    if (e == hipSuccess) e = hipEventRecord(c->ev[1], s);
-    if (e == hipSuccess) e = launch_transport(p, blocks, threads, diag, s);
-    if (e == hipSuccess) e = hipEventRecord(c->ev[2], s);
-    double* d_dose = nullptr;
-    double* d_sigma = nullptr;
-    if (e == hipSuccess && want_final) {
-        d_dose = out->on_device && out->dose && out->sigma ? out->dose : c->dose;
-        d_sigma = out->on_device && out->dose && out->sigma ? out->sigma : c->sigma;
-        e = launch_finalize(c->S, c->Q, ph.vox, ph.nv, ph.g.dx * ph.g.dy * ph.g.dz,
-                            n_histories + (accumulate ? c->tally_hist : 0), d_dose, d_sigma, red, s);
-    }
-    if (e == hipSuccess) e = hipEventRecord(c->ev[3], s);
-    unsigned char host_small[kSmallBytes];
-    if (e == hipSuccess) e = hipMemcpyAsync(host_small, c->small, kSmallBytes, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return c->hip_fail(e, "transport launch");
-    int err;
-    std::memcpy(&err, host_small + kOffErr, 4);
-    if (err) {
-        c->keys_clean = false;          // lanes stopped mid-history
-        c->tally_owner = -1;
-        return c->fail(err, err == MCD_E_OVERFLOW
-                                ? "particle stack or local counter overflow: raise stack_depth or tally_slots"
-                                : "device error");
-    }
-    c->tally_owner = phantom;
-    c->tally_hist = n_histories + (accumulate ? c->tally_hist : 0);
-
-    // outputs
-    const size_t vb = (size_t)ph.nv * sizeof(double);
-    const hipMemcpyKind k_out = out->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (out->dose && d_dose != out->dose) e = hipMemcpyAsync(out->dose, d_dose, vb, k_out, s);
-    if (e == hipSuccess && out->sigma && d_sigma != out->sigma)
-        e = hipMemcpyAsync(out->sigma, d_sigma, vb, k_out, s);
-    if (e == hipSuccess && out->S) e = hipMemcpyAsync(out->S, c->S, vb, k_out, s);
-    if (e == hipSuccess && out->Q) e = hipMemcpyAsync(out->Q, c->Q, vb, k_out, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return c->hip_fail(e, "result copy");
-
-    double bal[kBal];
-    std::memcpy(bal, host_small + kOffBal, sizeof bal);
-    out->eb.e_src = bal[0];
-    out->eb.e_csda = bal[1];
-    out->eb.e_local = bal[2];
-    out->eb.e_esc = bal[3];
-    out->eb.e_miss = bal[4];
-    out->eb.track_e = bal[5];
-    std::memcpy(out->counters, host_small + kOffCnt, sizeof out->counters);
-    double r3[3];
-    std::memcpy(r3, host_small + kOffRed, sizeof r3);
-    out->dmax = want_final ? r3[0] : 0.0;
-    out->sigma_bar = want_final && r3[2] > 0 ? r3[1] / r3[2] : 0.0;
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
-    out->kernel_ms = ms;
-    (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[3]);
-    out->total_ms = ms;
-    return MCD_OK;
-}

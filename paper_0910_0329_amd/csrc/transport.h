@@ -1,0 +1,732 @@
+// Device transport machine shared by every kernel of libmcdose (gfx950, wave64).
+//
+// The physics follows the DPM scheme the paper ports (Sec. 2.1): photons by
+// Woodcock tracking against a phantom majorant with Compton, photoelectric and
+// pair interactions; electrons and positrons by condensed-history segments
+// limited by the absorption energy, the next hard event, the random-hinge
+// budget, the voxel face and the energy-loss fraction, with CSDA loss from the
+// range table and hard Moller / bremsstrahlung events spawning secondaries.
+// Transport arithmetic is FP32.
+//
+// Random numbers: Philox4x32-10 keyed by (seed, request key); a particle's
+// counter is (history, lineage lo, lineage hi, block) and its i-th uniform is
+// word i mod 4 of block i / 4, as u = ((x >> 9) + 0.5) 2^-23 (exact in FP32).
+// Each particle keeps a ring of its two most recent blocks; a step refills the
+// ring once at its start, so the Philox rounds run at one place per step.
+//
+// The machine is written once and specialised by the kernels through CRTP:
+// a derived lane supplies deposit(), spawn() and the per-history bookkeeping.
+#pragma once
+
+#include "engine.h"
+#include "mcdose.h"
+
+namespace mcd {
+
+#define DEV __device__ __forceinline__
+
+constexpr float kMC2 = 0.51099895f;
+constexpr float kLn2 = 0.693147180559945309f;
+constexpr float kInf = __builtin_huge_valf();
+
+enum { PHOTON = 0, ELECTRON = 1, POSITRON = 2, DEAD = -1 };
+enum { LIM_E, LIM_H, LIM_K, LIM_B, LIM_F };
+// Event codes of the per-particle hash (diagnostics).
+enum { EV_VIRTUAL = 1, EV_COMPTON, EV_PHOTO, EV_PAIR, EV_PAIR_VOID, EV_G_ESCAPE, EV_G_ABSORB,
+       EV_SEG = 10, EV_MOLLER = 20, EV_BREMS, EV_MOLLER_VOID, EV_E_ESCAPE };
+
+DEV float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+DEV float neg_ln(float u) { return -__log2f(u) * kLn2; }
+
+// Philox4x32-10 (Salmon et al., SC'11), in place on the counter.
+DEV void philox10(uint32_t k0, uint32_t k1, uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                  uint32_t& c3)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+}
+
+// One particle in flight with its random stream.
+struct Part {
+    float x, y, z, u, v, w, e;
+    int type;
+    uint32_t h;              // history
+    uint32_t slot;           // request slot (batched kernels)
+    uint32_t l0, l1;         // lineage
+    uint32_t d;              // next draw index
+    uint32_t g;              // next block to generate; blocks g-2, g-1 are in the ring
+    uint32_t nsp;            // secondaries spawned from this stream
+    uint32_t r0, r1, r2, r3, r4, r5, r6, r7;  // ring: block k in words 4(k&1)..4(k&1)+3
+    int ix, iy, iz;          // electron voxel (state, advanced across faces)
+    float nh, xi, kap;       // hard-event mfps to go, hinge fraction, hinge budget
+    int before;              // 1 before the hinge of the current step
+};
+
+// Particle record in a stack or queue: 48 bytes.
+//   f0 = (x, y, z, E), f1 = (u, v, w, bits(type | slot << 4)), f2 = bits(l0, l1, h, d)
+DEV void store_rec(char* base, const Part& q)
+{
+    float4* r = (float4*)base;
+    r[0] = make_float4(q.x, q.y, q.z, q.e);
+    r[1] = make_float4(q.u, q.v, q.w, __uint_as_float((uint32_t)q.type | (q.slot << 4)));
+    r[2] = make_float4(__uint_as_float(q.l0), __uint_as_float(q.l1), __uint_as_float(q.h),
+                       __uint_as_float(q.d));
+}
+
+DEV void load_rec(const char* base, Part& q)
+{
+    const float4* r = (const float4*)base;
+    const float4 a = r[0], b = r[1], c = r[2];
+    q.x = a.x; q.y = a.y; q.z = a.z; q.e = a.w;
+    q.u = b.x; q.v = b.y; q.w = b.z;
+    const uint32_t ts = __float_as_uint(b.w);
+    q.type = (int)(ts & 15u);
+    q.slot = ts >> 4;
+    q.l0 = __float_as_uint(c.x);
+    q.l1 = __float_as_uint(c.y);
+    q.h = __float_as_uint(c.z);
+    q.d = __float_as_uint(c.w);
+    q.g = q.d >> 2;
+    q.nsp = 0;
+}
+
+// Read-only view of tables staged in LDS plus the phantom geometry.
+struct Env {
+    const float4* phot;      // LDS [n_mat * 512]
+    const float4* elec;      // LDS [n_mat * 512]
+    const float* maj;        // LDS [512]
+    const float* r_abs;      // LDS [kMaxMat]
+    uint32_t seed, key;      // Philox key of the particle being transported
+};
+
+template <class D, bool DIAG>
+struct Transport {
+    // Bound to the kernel argument itself, so that geometry and table scalars
+    // stay wave-uniform scalar loads.
+    const KGeom& gm;
+    Env env;
+    double e_src, e_csda, e_local, e_esc, e_miss, track;
+    uint32_t c[kCounters];
+    uint64_t p_hash;
+    int failed;
+
+    DEV explicit Transport(const KGeom& g) : gm(g) {}
+    DEV D& self() { return *static_cast<D*>(this); }
+    DEV const KGeom& G() const { return gm; }
+
+    DEV void init_base()
+    {
+        e_src = e_csda = e_local = e_esc = e_miss = track = 0.0;
+        failed = 0;
+        p_hash = 0;
+        if (DIAG)
+            for (int i = 0; i < kCounters; ++i) c[i] = 0;
+    }
+
+    DEV void count(int i) { if (DIAG) ++c[i]; }
+    DEV void ev(uint32_t code) { if (DIAG) p_hash = (p_hash ^ code) * 0x100000001b3ull; }
+
+    // ------------------------------------------------------------- random
+    DEV void refill(Part& q)
+    {
+        uint32_t c0 = q.h, c1 = q.l0, c2 = q.l1, c3 = q.g;
+        philox10(env.seed, env.key, c0, c1, c2, c3);
+        if (q.g & 1u) {
+            q.r4 = c0; q.r5 = c1; q.r6 = c2; q.r7 = c3;
+        } else {
+            q.r0 = c0; q.r1 = c1; q.r2 = c2; q.r3 = c3;
+        }
+        ++q.g;
+        count(MCD_C_PHILOX);
+    }
+
+    // Keeps at least five uniforms ahead; called once at the start of a step.
+    DEV void prefetch(Part& q)
+    {
+        if ((q.d >> 2) + 1u >= q.g) refill(q);
+    }
+
+    DEV float uni(Part& q)
+    {
+        if ((q.d >> 2) >= q.g) refill(q);
+        const uint32_t k = q.d & 3u;
+        uint32_t x;
+        if ((q.d >> 2) & 1u) x = k == 0 ? q.r4 : (k == 1 ? q.r5 : (k == 2 ? q.r6 : q.r7));
+        else x = k == 0 ? q.r0 : (k == 1 ? q.r1 : (k == 2 ? q.r2 : q.r3));
+        ++q.d;
+        return ((float)(x >> 9) + 0.5f) * 0x1p-23f;
+    }
+
+    DEV void child_lineage(Part& q, uint32_t& o0, uint32_t& o1)
+    {
+        uint32_t c0 = q.h, c1 = q.l0, c2 = q.l1, c3 = 0x80000000u | q.nsp;
+        philox10(env.seed, env.key, c0, c1, c2, c3);
+        o0 = c0;
+        o1 = c1;
+        ++q.nsp;
+        count(MCD_C_PHILOX);
+    }
+
+    // ------------------------------------------------------------ tables
+    DEV void eidx(float e, int& i, float& fr) const
+    {
+        const DevTables& t = G().t;
+        e = fminf(fmaxf(e, t.emin), t.emax);
+        const float x = (__log2f(e) - t.l2_emin) * t.inv_dl2;
+        i = min(max((int)x, 0), kNE - 2);
+        fr = x - (float)i;
+    }
+
+    DEV float range_at(int m, float e) const
+    {
+        int i;
+        float fr;
+        eidx(e, i, fr);
+        const float a = env.elec[m * kNE + i].x, b = env.elec[m * kNE + i + 1].x;
+        return a + (b - a) * fr;
+    }
+
+    // Inverse of the interpolated range of material m: the node interval holding
+    // r is found by walking down from interval i0 (r does not exceed the range
+    // at the start of the segment), then that linear piece is solved for log E.
+    DEV float range_inverse(int m, float r, int i0) const
+    {
+        const float4* el = env.elec + m * kNE;
+        int j = i0;
+        while (j > 0 && el[j].x > r) --j;
+        if (el[j].x > r) return G().t.emin;
+        while (j < kNE - 2 && el[j + 1].x <= r) ++j;
+        const float r0 = el[j].x, r1 = el[j + 1].x;
+        const float fr = fminf(fdiv(r - r0, r1 - r0), 1.0f);
+        return exp2f(G().t.l2_emin + ((float)j + fr) * G().t.dl2);
+    }
+
+    // --------------------------------------------------------- geometry
+    DEV bool inside(float x, float y, float z) const
+    {
+        const KGeom& g = G();
+        return x >= g.x0 && x < g.x1 && y >= g.y0 && y < g.y1 && z >= g.z0 && z < g.z1;
+    }
+
+    DEV void floor_voxel(float x, float y, float z, int& ix, int& iy, int& iz) const
+    {
+        const KGeom& g = G();
+        ix = min(max((int)floorf((x - g.x0) * g.idx), 0), g.nx - 1);
+        iy = min(max((int)floorf((y - g.y0) * g.idy), 0), g.ny - 1);
+        iz = min(max((int)floorf((z - g.z0) * g.idz), 0), g.nz - 1);
+    }
+
+    DEV int lin(int ix, int iy, int iz) const { return (iz * G().ny + iy) * G().nx + ix; }
+
+    DEV void local(const Part& q, int v, float e)
+    {
+        count(MCD_C_LOCAL);
+        e_local += (double)e;
+        self().deposit(q, v, e);
+    }
+
+    // ------------------------------------------------------ secondaries
+    // A secondary below its absorption energy is deposited on the spot (a
+    // positron then annihilates with uniforms of the stream q); above it, it
+    // gets q's next child lineage and is handed to the lane's spawn policy.
+    DEV void emit_photon(Part& q, float e, float x, float y, float z, float u, float v, float w,
+                         int vox)
+    {
+        if (e <= G().t.e_abs_g) {
+            local(q, vox, e);
+            return;
+        }
+        Part s;
+        s.type = PHOTON;
+        s.e = e;
+        s.x = x; s.y = y; s.z = z;
+        s.u = u; s.v = v; s.w = w;
+        s.h = q.h;
+        s.slot = q.slot;
+        s.d = 0;
+        child_lineage(q, s.l0, s.l1);
+        count(MCD_C_SPAWNS);
+        self().spawn(s);
+    }
+
+    DEV void annihilate(Part& q, float x, float y, float z, int vox)
+    {
+        const float cost = 2.f * uni(q) - 1.f;
+        const float ph = uni(q);
+        const float sint = sqrtf(fmaxf(0.f, 1.f - cost * cost));
+        const float cp = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
+        const float dx = sint * cp, dy = sint * sph;
+        emit_photon(q, kMC2, x, y, z, dx, dy, cost, vox);
+        emit_photon(q, kMC2, x, y, z, -dx, -dy, -cost, vox);
+    }
+
+    DEV void emit_charged(Part& q, int type, float e, float x, float y, float z, float u,
+                          float v, float w, int vox)
+    {
+        if (e <= G().t.e_abs_e) {
+            local(q, vox, e);
+            if (type == POSITRON) annihilate(q, x, y, z, vox);
+            return;
+        }
+        Part s;
+        s.type = type;
+        s.e = e;
+        s.x = x; s.y = y; s.z = z;
+        s.u = u; s.v = v; s.w = w;
+        s.h = q.h;
+        s.slot = q.slot;
+        s.d = 0;
+        child_lineage(q, s.l0, s.l1);
+        count(MCD_C_SPAWNS);
+        self().spawn(s);
+    }
+
+    // ---------------------------------------------------------- rotation
+    // Rotates (u, v, w) by polar cosine cost and azimuth (cos, sin) = (cp, sph).
+    DEV static void rotate(float& u, float& v, float& w, float cost, float cp, float sph)
+    {
+        const float sint = sqrtf(fmaxf(0.f, 1.f - cost * cost));
+        const float s = sqrtf(u * u + v * v);
+        float nu, nv, nw;
+        if (s < 1e-7f) {
+            nu = sint * cp;
+            nv = sint * sph;
+            nw = (w > 0.f ? 1.f : -1.f) * cost;
+        } else {
+            const float is = __builtin_amdgcn_rcpf(s);
+            nu = u * cost + sint * (u * w * cp - v * sph) * is;
+            nv = v * cost + sint * (v * w * cp + u * sph) * is;
+            nw = w * cost - s * sint * cp;
+        }
+        const float n = __builtin_amdgcn_rsqf(nu * nu + nv * nv + nw * nw);
+        u = nu * n;
+        v = nv * n;
+        w = nw * n;
+    }
+
+    // ------------------------------------------------------- particles
+    // Start of transport of a particle taken from a stack or queue (or the
+    // source): an electron is born with its hard-event mfps and hinge position.
+    DEV void start_particle(Part& q)
+    {
+        if (DIAG) p_hash = (0xcbf29ce484222325ull ^ ((uint64_t)q.l1 << 32 | q.l0)) * 0x100000001b3ull;
+        if (q.type != PHOTON) {
+            floor_voxel(q.x, q.y, q.z, q.ix, q.iy, q.iz);
+            prefetch(q);
+            q.nh = neg_ln(uni(q));
+            q.xi = uni(q);
+            q.kap = q.xi * G().t.kappa_step;
+            q.before = 1;
+        }
+    }
+
+    DEV void end_particle(Part& q)
+    {
+        q.type = DEAD;
+        self().particle_done(q, p_hash);
+    }
+
+    // Source particle of history q.h from block 0 of its primary stream
+    // (u0, u1: field position; u2: histogram bin; u3: position in the bin).
+    // Returns with q.type == DEAD when the primary misses the phantom or is
+    // absorbed on the spot.
+    DEV void start_history(Part& q, const DevSource& s, const float* edges, const float* cdf)
+    {
+        const KGeom& g = G();
+        q.l0 = q.l1 = 0;
+        q.d = 0;
+        q.g = 0;
+        q.nsp = 0;
+        const float u0 = uni(q), u1 = uni(q), u2 = uni(q), u3 = uni(q);
+        float e;
+        if (s.energy_kind == MCD_MONO) {
+            e = s.e0;
+        } else {
+            int lo = 0, hi = s.n_bins - 1;      // first bin whose CDF exceeds u2
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (cdf[mid] > u2) hi = mid; else lo = mid + 1;
+            }
+            e = edges[lo] + u3 * (edges[lo + 1] - edges[lo]);
+        }
+        float x, y, u = 0.f, v = 0.f, w = 1.f;
+        if (s.beam_kind == MCD_PENCIL) {
+            x = s.pos[0];
+            y = s.pos[1];
+        } else {
+            x = s.field[0] - s.field[2] + 2.f * s.field[2] * u0;
+            y = s.field[1] - s.field[3] + 2.f * s.field[3] * u1;
+            const float dx = x - s.pos[0], dy = y - s.pos[1], dz = g.z0 - s.pos[2];
+            const float n = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+            u = dx * n;
+            v = dy * n;
+            w = dz * n;
+        }
+        count(MCD_C_HISTORIES);
+        e_src += (double)e + s.extra;
+        q.type = DEAD;
+        if (!(x >= g.x0 && x < g.x1 && y >= g.y0 && y < g.y1 && w > 0.f)) {
+            e_miss += (double)e + s.extra;
+            count(MCD_C_MISSES);
+            return;
+        }
+        q.x = x; q.y = y; q.z = g.z0;
+        q.u = u; q.v = v; q.w = w;
+        q.e = e;
+        q.d = 4;                              // transport starts at block 1
+        const float cut = s.particle == PHOTON ? g.t.e_abs_g : g.t.e_abs_e;
+        if (e <= cut) {
+            int ix, iy, iz;
+            floor_voxel(q.x, q.y, q.z, ix, iy, iz);
+            const int vx = lin(ix, iy, iz);
+            local(q, vx, e);
+            if (s.particle == POSITRON) annihilate(q, q.x, q.y, q.z, vx);
+            self().flush_particle(q);
+            return;
+        }
+        q.type = s.particle;
+    }
+
+    // One Woodcock flight and, if the stop is real, its interaction.
+    DEV void photon_step(Part& q)
+    {
+        prefetch(q);
+        int i;
+        float fr;
+        eidx(q.e, i, fr);
+        const float mu_max = env.maj[i] + (env.maj[i + 1] - env.maj[i]) * fr;
+        const float s = fdiv(neg_ln(uni(q)), mu_max);
+        count(MCD_C_FLIGHTS);
+        q.x += s * q.u;
+        q.y += s * q.v;
+        q.z += s * q.w;
+        if (!inside(q.x, q.y, q.z)) {
+            ev(EV_G_ESCAPE);
+            e_esc += (double)q.e;
+            count(MCD_C_ESCAPES);
+            self().escaped(q);
+            end_particle(q);
+            return;
+        }
+        int ix, iy, iz;
+        floor_voxel(q.x, q.y, q.z, ix, iy, iz);
+        const int vx = lin(ix, iy, iz);
+        const uint2 vd = G().vox[vx];
+        const float rho = __uint_as_float(vd.x);
+        const int m = (int)vd.y;
+        const float4 a = env.phot[m * kNE + i], b = env.phot[m * kNE + i + 1];
+        const float mu_c = rho * (a.x + (b.x - a.x) * fr);
+        const float mu_pe = rho * (a.y + (b.y - a.y) * fr);
+        const float mu_pp = rho * (a.z + (b.z - a.z) * fr);
+        const float xs = uni(q) * mu_max;
+        if (xs < mu_c) {
+            ev(EV_COMPTON);
+            count(MCD_C_COMPTON);
+            compton(q, vx);
+        } else if (xs < mu_c + mu_pe) {
+            ev(EV_PHOTO);
+            count(MCD_C_PHOTO);
+            emit_charged(q, ELECTRON, q.e, q.x, q.y, q.z, q.u, q.v, q.w, vx);
+            end_particle(q);
+        } else if (xs < mu_c + mu_pe + mu_pp) {
+            if (q.e > 2.f * kMC2) {
+                ev(EV_PAIR);
+                count(MCD_C_PAIR);
+                const float ttot = q.e - 2.f * kMC2;
+                const float tm = uni(q) * ttot;
+                const float tp = ttot - tm;
+                emit_charged(q, ELECTRON, tm, q.x, q.y, q.z, q.u, q.v, q.w, vx);
+                emit_charged(q, POSITRON, tp, q.x, q.y, q.z, q.u, q.v, q.w, vx);
+                end_particle(q);
+            } else {
+                ev(EV_PAIR_VOID);
+                count(MCD_C_VOID);
+            }
+        } else {
+            ev(EV_VIRTUAL);
+            count(MCD_C_VIRTUAL);
+        }
+    }
+
+    // Klein-Nishina by composition and rejection (three uniforms per try).
+    DEV void compton(Part& q, int vx)
+    {
+        const float e = q.e;
+        const float k = fdiv(e, kMC2);
+        const float tmin = __builtin_amdgcn_rcpf(1.f + 2.f * k);
+        const float a1 = __log2f(1.f + 2.f * k) * kLn2;
+        const float a2 = 2.f * k * (1.f + k) * tmin * tmin;
+        const float l2tmin = __log2f(tmin);
+        float tau, cost;
+        for (;;) {
+            const float ua = uni(q), ub = uni(q), uc = uni(q);
+            count(MCD_C_COMPTON_TRIES);
+            if (ua * (a1 + a2) < a1) tau = exp2f(ub * l2tmin);
+            else tau = sqrtf(tmin * tmin + ub * (1.f - tmin * tmin));
+            cost = 1.f - fdiv(1.f - tau, k * tau);
+            const float sin2 = 1.f - cost * cost;
+            if (uc <= 1.f - fdiv(tau * sin2, 1.f + tau * tau)) break;
+        }
+        const float ph = uni(q);
+        const float cp = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
+        const float te = e - tau * e;          // electron energy; the photon keeps
+        const float e1 = e - te;               // exactly the rest (e1 + te == e)
+        const float pe2 = e * e + e1 * e1 - 2.f * e * e1 * cost;
+        float cose = pe2 > 0.f ? (e - e1 * cost) * __builtin_amdgcn_rsqf(pe2) : 1.f;
+        cose = fminf(fmaxf(cose, -1.f), 1.f);
+        float du = q.u, dv = q.v, dw = q.w;
+        rotate(du, dv, dw, cose, -cp, -sph);   // azimuth phi + pi
+        emit_charged(q, ELECTRON, te, q.x, q.y, q.z, du, dv, dw, vx);
+        rotate(q.u, q.v, q.w, cost, cp, sph);
+        q.e = e1;
+        if (e1 <= G().t.e_abs_g) {
+            ev(EV_G_ABSORB);
+            local(q, vx, e1);
+            end_particle(q);
+        }
+    }
+
+    // Distance along the direction to the exit face of the electron's voxel.
+    DEV float boundary(const Part& q, int& axis) const
+    {
+        const KGeom& g = G();
+        float best = kInf;
+        axis = 0;
+        if (q.u != 0.f) {
+            const float f = g.x0 + (float)(q.u > 0.f ? q.ix + 1 : q.ix) * g.dx;
+            best = fmaxf(0.f, fdiv(f - q.x, q.u));
+        }
+        if (q.v != 0.f) {
+            const float f = g.y0 + (float)(q.v > 0.f ? q.iy + 1 : q.iy) * g.dy;
+            const float dd = fmaxf(0.f, fdiv(f - q.y, q.v));
+            if (dd < best) { best = dd; axis = 1; }
+        }
+        if (q.w != 0.f) {
+            const float f = g.z0 + (float)(q.w > 0.f ? q.iz + 1 : q.iz) * g.dz;
+            const float dd = fmaxf(0.f, fdiv(f - q.z, q.w));
+            if (dd < best) { best = dd; axis = 2; }
+        }
+        return best;
+    }
+
+    // One condensed-history segment inside the current voxel.
+    DEV void electron_step(Part& q)
+    {
+        prefetch(q);
+        const KGeom& g = G();
+        const int vx = lin(q.ix, q.iy, q.iz);
+        const uint2 vd = g.vox[vx];
+        const float rho = __uint_as_float(vd.x);
+        const float irho = __builtin_amdgcn_rcpf(rho);
+        const int m = (int)vd.y;
+        const float T = q.e;
+        int i;
+        float fr;
+        eidx(T, i, fr);
+        const float4 a = env.elec[m * kNE + i], b = env.elec[m * kNE + i + 1];
+        const float rt = a.x + (b.x - a.x) * fr;
+        const float lam = a.y + (b.y - a.y) * fr;
+        const float sh = (a.z + (b.z - a.z) * fr) + (a.w + (b.w - a.w) * fr);
+        // the five limits, ties resolved in the order E, h, kappa, b, f
+        float l = fmaxf(0.f, (rt - env.r_abs[m]) * irho);
+        int lim = LIM_E;
+        const float l_h = sh > 0.f ? fmaxf(0.f, fdiv(q.nh, rho * sh)) : kInf;
+        if (l_h < l) { l = l_h; lim = LIM_H; }
+        const float l_k = fmaxf(0.f, fdiv(q.kap, rho * lam));
+        if (l_k < l) { l = l_k; lim = LIM_K; }
+        int axis;
+        const float l_b = boundary(q, axis);
+        if (l_b < l) { l = l_b; lim = LIM_B; }
+        const float l_f = (rt - range_at(m, (1.f - g.t.f_e) * T)) * irho;
+        if (l_f < l) { l = l_f; lim = LIM_F; }
+        // move and lose energy continuously
+        q.x += l * q.u;
+        q.y += l * q.v;
+        q.z += l * q.w;
+        float tn;
+        if (lim == LIM_E) tn = T > g.t.e_abs_e ? g.t.e_abs_e : T;
+        else tn = fminf(T, range_inverse(m, rt - rho * l, i));
+        const float dep = T - tn;
+        e_csda += (double)dep;
+        self().deposit(q, vx, dep);
+        track += (double)l;
+        self().add_track(q, l);
+        q.nh -= l * rho * sh;
+        q.kap -= l * rho * lam;
+        q.e = tn;
+        count(MCD_C_SEGMENTS);
+        count(MCD_C_SEG_E + lim);
+        ev(EV_SEG + (uint32_t)lim);
+
+        if (lim == LIM_E) {
+            local(q, vx, tn);
+            if (q.type == POSITRON) annihilate(q, q.x, q.y, q.z, vx);
+            end_particle(q);
+        } else if (lim == LIM_H) {
+            hard_event(q, m, vx);
+        } else if (lim == LIM_K) {
+            if (q.before) {
+                count(MCD_C_HINGES);
+                const float u = uni(q);
+                const float A = g.t.a_hinge;
+                const float mu = fdiv(A * u, 1.f + A - u);
+                const float ph = uni(q);
+                rotate(q.u, q.v, q.w, 1.f - 2.f * mu, __builtin_amdgcn_cosf(ph),
+                       __builtin_amdgcn_sinf(ph));
+                q.kap = (1.f - q.xi) * g.t.kappa_step;
+                q.before = 0;
+            } else {
+                q.xi = uni(q);
+                q.kap = q.xi * g.t.kappa_step;
+                q.before = 1;
+            }
+        } else if (lim == LIM_B) {
+            bool out;
+            if (axis == 0) {
+                q.ix += q.u > 0.f ? 1 : -1;
+                out = q.ix < 0 || q.ix >= g.nx;
+            } else if (axis == 1) {
+                q.iy += q.v > 0.f ? 1 : -1;
+                out = q.iy < 0 || q.iy >= g.ny;
+            } else {
+                q.iz += q.w > 0.f ? 1 : -1;
+                out = q.iz < 0 || q.iz >= g.nz;
+            }
+            if (out) {
+                ev(EV_E_ESCAPE);
+                e_esc += (double)q.e + (q.type == POSITRON ? 2.0 * (double)kMC2 : 0.0);
+                count(MCD_C_ESCAPES);
+                self().escaped(q);
+                end_particle(q);
+            }
+        }
+    }
+
+    DEV void hard_event(Part& q, int m, int vx)
+    {
+        const KGeom& g = G();
+        float T = q.e;
+        int i;
+        float fr;
+        eidx(T, i, fr);
+        const float4 a = env.elec[m * kNE + i], b = env.elec[m * kNE + i + 1];
+        const float sm = a.z + (b.z - a.z) * fr;
+        const float sb = a.w + (b.w - a.w) * fr;
+        if (uni(q) * (sm + sb) < sm) {
+            if (T <= 2.f * g.t.w_cc) {
+                ev(EV_MOLLER_VOID);
+                count(MCD_C_VOID);
+            } else {
+                ev(EV_MOLLER);
+                count(MCD_C_MOLLER);
+                const float e0 = fdiv(g.t.w_cc, T);
+                const float tau = fdiv(T, kMC2);
+                const float gg = fdiv(tau, tau + 1.f);
+                const float c = fdiv(2.f * tau + 1.f, (tau + 1.f) * (tau + 1.f));
+                float eps;
+                for (;;) {
+                    eps = fdiv(e0, 1.f - uni(q) * (1.f - 2.f * e0));
+                    const float ua = uni(q);
+                    count(MCD_C_MOLLER_TRIES);
+                    const float r = fdiv(eps, 1.f - eps);
+                    const float gv = 1.f + r * r + gg * gg * eps * eps - c * r;
+                    if (ua * 2.25f <= gv) break;
+                }
+                const float ph = uni(q);
+                const float cp = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
+                const float tn = T - eps * T;      // primary keeps exactly T - W
+                const float wd = T - tn;
+                const float cs = sqrtf(fdiv(wd * (T + 2.f * kMC2), T * (wd + 2.f * kMC2)));
+                const float cpr = sqrtf(fdiv(tn * (T + 2.f * kMC2), T * (tn + 2.f * kMC2)));
+                float du = q.u, dv = q.v, dw = q.w;
+                rotate(du, dv, dw, fminf(cs, 1.f), -cp, -sph);
+                emit_charged(q, ELECTRON, wd, q.x, q.y, q.z, du, dv, dw, vx);
+                rotate(q.u, q.v, q.w, fminf(cpr, 1.f), cp, sph);
+                T = tn;
+            }
+        } else {
+            ev(EV_BREMS);
+            count(MCD_C_BREMS);
+            const float w = fminf(g.t.w_cr * exp2f(uni(q) * __log2f(fdiv(T, g.t.w_cr))), T);
+            (void)uni(q);                          // azimuth, drawn for the draw order
+            const float tn = T - w;
+            emit_photon(q, T - tn, q.x, q.y, q.z, q.u, q.v, q.w, vx);
+            T = tn;
+        }
+        q.e = T;
+        if (T <= g.t.e_abs_e) {
+            local(q, vx, T);
+            if (q.type == POSITRON) annihilate(q, q.x, q.y, q.z, vx);
+            end_particle(q);
+            return;
+        }
+        q.nh = neg_ln(uni(q));
+    }
+
+    DEV void step(Part& q)
+    {
+        if (q.type == PHOTON) photon_step(q);
+        else electron_step(q);
+    }
+
+    // Wave-level reduction of the energy balance and counters, one atomic per wave.
+    DEV void reduce_out(double* bal, unsigned long long* cnt)
+    {
+        double b[kBal] = {e_src, e_csda, e_local, e_esc, e_miss, track};
+#pragma unroll
+        for (int k = 0; k < kBal; ++k)
+            for (int o = 32; o > 0; o >>= 1) b[k] += __shfl_xor(b[k], o, 64);
+        if ((threadIdx.x & 63) == 0)
+            for (int k = 0; k < kBal; ++k) unsafeAtomicAdd(&bal[k], b[k]);
+        if (DIAG) {
+            for (int k = 0; k < kCounters; ++k) {
+                if (k == MCD_C_MAX_STACK) {
+                    uint32_t v = c[k];
+                    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+                    if ((threadIdx.x & 63) == 0) atomicMax(&cnt[k], (unsigned long long)v);
+                } else {
+                    unsigned long long v = c[k];
+                    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                    if ((threadIdx.x & 63) == 0 && v) atomicAdd(&cnt[k], v);
+                }
+            }
+        }
+    }
+};
+
+// Stages the material tables and the majorant into LDS (dynamic shared memory
+// laid out as phot | elec | maj | r_abs | extra floats).
+DEV void stage_tables(const KGeom& g, float4* lds, Env& env, float** extra)
+{
+    const int nt = g.t.n_mat * kNE;
+    float4* s_phot = lds;
+    float4* s_elec = lds + nt;
+    float* s_maj = (float*)(lds + 2 * nt);
+    float* s_rabs = s_maj + kNE;
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+        s_phot[i] = g.t.phot[i];
+        s_elec[i] = g.t.elec[i];
+    }
+    for (int i = threadIdx.x; i < kNE; i += blockDim.x) s_maj[i] = g.maj[i];
+    for (int i = threadIdx.x; i < kMaxMat; i += blockDim.x) s_rabs[i] = g.t.r_abs[i];
+    env.phot = s_phot;
+    env.elec = s_elec;
+    env.maj = s_maj;
+    env.r_abs = s_rabs;
+    *extra = s_rabs + kMaxMat;
+}
+
+}  // namespace mcd

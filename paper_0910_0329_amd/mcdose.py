@@ -52,7 +52,11 @@ class Opts(C.Structure):
                 ("grid_blocks", C.c_int32), ("stack_depth", C.c_int32),
                 ("tally_slots", C.c_int32), ("diagnostics", C.c_int32),
                 ("accumulate", C.c_int32), ("history_records", C.c_void_p),
-                ("lockstep", C.c_int32), ("reserved", C.c_int32)]
+                ("lockstep", C.c_int32), ("kernel", C.c_int32), ("tally_fp32", C.c_int32),
+                ("chunk_per_lane", C.c_int32), ("use_graph", C.c_int32), ("regroup", C.c_int32)]
+
+
+KERNEL_REGROUPED, KERNEL_PLAIN = 0, 1
 
 
 class Result(C.Structure):
@@ -60,6 +64,11 @@ class Result(C.Structure):
                 ("on_device", C.c_int32), ("eb", EnergyBalance),
                 ("counters", C.c_uint64 * NCOUNT), ("dmax", C.c_double),
                 ("sigma_bar", C.c_double), ("kernel_ms", C.c_double), ("total_ms", C.c_double)]
+
+
+class BatchItem(C.Structure):
+    _fields_ = [("src", Source), ("n_histories", C.c_uint64), ("request_key", C.c_uint32),
+                ("reserved", C.c_uint32), ("out", C.POINTER(Result))]
 
 
 HISTORY_DTYPE = np.dtype([("edep", "<f8"), ("track_e", "<f8"), ("hash", "<u8"),
@@ -74,6 +83,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_0910_0329_amd.build`")
+        # Load torch's HIP runtime first so that the library binds to the same
+        # one (two runtimes in one process do not share devices).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32 = C.c_void_p, C.c_int32
         L.mcd_create.argtypes = [C.c_int, C.c_uint64, C.POINTER(vp)]
@@ -84,6 +99,8 @@ def lib():
         L.mcd_unload_phantom.argtypes = [vp, i32]
         L.mcd_simulate.argtypes = [vp, i32, C.POINTER(Source), C.c_uint64, C.c_uint64, C.c_uint32,
                                    C.POINTER(Opts), C.POINTER(Result), vp]
+        L.mcd_simulate_batch.argtypes = [vp, i32, C.POINTER(BatchItem), i32, C.c_uint64,
+                                         C.POINTER(Opts), C.POINTER(Result), vp]
         L.mcd_status_string.argtypes = [C.c_int]
         L.mcd_status_string.restype = C.c_char_p
         L.mcd_last_error.argtypes = [vp]
@@ -93,8 +110,8 @@ def lib():
 
 
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_load_materials", "mcd_unload_materials",
-            "mcd_load_phantom", "mcd_unload_phantom", "mcd_simulate", "mcd_status_string",
-            "mcd_last_error")
+            "mcd_load_phantom", "mcd_unload_phantom", "mcd_simulate", "mcd_simulate_batch",
+            "mcd_status_string", "mcd_last_error")
 
 
 def make_source(src) -> Source:
@@ -186,11 +203,22 @@ class Engine:
         if history_records is not None:
             o.history_records = history_records.data_ptr()
             o.diagnostics = 1
-        r = Result()
-        bufs = {}
         if n_vox is None and (want_dose or want_tallies):
             raise ValueError("n_vox is required for dose or tally outputs")
-        names = (("dose", "sigma") if want_dose else ()) + (("S", "Q") if want_tallies else ())
+        tallies = ("S", "Q") if o.kernel == KERNEL_PLAIN else ("S",)
+        names = (("dose", "sigma") if want_dose else ()) + (tallies if want_tallies else ())
+        r, bufs, stream = self._outputs(names, n_vox, device_out, stream)
+        rc = lib().mcd_simulate(self._h, phantom, C.byref(s), n, seed, key, C.byref(o), C.byref(r),
+                                _stream_ptr(stream))
+        self._check(rc, "mcd_simulate")
+        out = dict(bufs)
+        out.update(_scalars(r))
+        out["n"] = n
+        return out
+
+    def _outputs(self, names, n_vox, device_out, stream):
+        r = Result()
+        bufs = {}
         if device_out:
             import torch
             for nm in names:
@@ -204,16 +232,45 @@ class Engine:
                 bufs[nm] = np.empty(n_vox, dtype=np.float64)
                 setattr(r, nm, bufs[nm].ctypes.data)
             r.on_device = 0
-        rc = lib().mcd_simulate(self._h, phantom, C.byref(s), n, seed, key, C.byref(o), C.byref(r),
-                                _stream_ptr(stream))
-        self._check(rc, "mcd_simulate")
-        eb = r.eb
-        out = dict(bufs)
-        out.update({
-            "bal": {"E_src": eb.e_src, "E_csda": eb.e_csda, "E_local": eb.e_local,
-                    "E_esc": eb.e_esc, "E_miss": eb.e_miss, "track_e": eb.track_e},
-            "cnt": dict(zip(COUNT_NAMES, (int(x) for x in r.counters))),
-            "dmax": r.dmax, "sigma_bar": r.sigma_bar, "kernel_ms": r.kernel_ms,
-            "total_ms": r.total_ms, "n": n,
-        })
-        return out
+        return r, bufs, stream
+
+    def simulate_batch(self, phantom: int, items, seed: int, *, n_vox: int, device_out: bool = True,
+                       want_dose: bool = True, want_tallies: bool = False, stream=None, **opts):
+        """items: sequence of (source, n_histories, request_key).  Returns the
+        per-item outputs (dose, sigma[, S], dmax, sigma_bar) and the batch totals."""
+        o = make_opts(**opts)
+        n = len(items)
+        arr = (BatchItem * n)()
+        results = [None] * n
+        per = []
+        names = (("dose", "sigma") if want_dose else ()) + (("S",) if want_tallies else ())
+        for i, (src, nh, key) in enumerate(items):
+            r, bufs, stream = self._outputs(names, n_vox, device_out, stream)
+            results[i] = r
+            per.append(bufs)
+            arr[i].src = make_source(src)
+            arr[i].n_histories = nh
+            arr[i].request_key = key
+            arr[i].out = C.pointer(r)
+        tot = Result()
+        rc = lib().mcd_simulate_batch(self._h, phantom, arr, n, seed, C.byref(o), C.byref(tot),
+                                      _stream_ptr(stream))
+        self._check(rc, "mcd_simulate_batch")
+        outs = []
+        for r, bufs in zip(results, per):
+            d = dict(bufs)
+            d["dmax"] = r.dmax
+            d["sigma_bar"] = r.sigma_bar
+            outs.append(d)
+        return outs, _scalars(tot)
+
+
+def _scalars(r: Result) -> dict:
+    eb = r.eb
+    return {
+        "bal": {"E_src": eb.e_src, "E_csda": eb.e_csda, "E_local": eb.e_local,
+                "E_esc": eb.e_esc, "E_miss": eb.e_miss, "track_e": eb.track_e},
+        "cnt": dict(zip(COUNT_NAMES, (int(x) for x in r.counters))),
+        "dmax": r.dmax, "sigma_bar": r.sigma_bar, "kernel_ms": r.kernel_ms,
+        "total_ms": r.total_ms,
+    }
