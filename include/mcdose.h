@@ -18,9 +18,9 @@
  *     exception or abort crosses this interface.
  *   - Host pointers are read during the call and may be freed on return.
  *   - Device pointers are HIP device addresses on the context's device.
- *   - A context is not thread-safe except for the serving calls
- *     (mcd_submit / mcd_poll / mcd_wait / mcd_cancel), which may be called
- *     from any thread.
+ *   - Calls on one context may come from several threads: blocking runs and
+ *     serving epochs take turns on the device; table and phantom loads wait
+ *     for the run in progress.  mcd_destroy must not overlap other calls.
  */
 #ifndef MCDOSE_H
 #define MCDOSE_H
@@ -215,7 +215,88 @@ typedef struct {
 int mcd_simulate_batch(mcd_ctx* ctx, int32_t phantom, const mcd_batch_item* items, int32_t n_items,
                        uint64_t seed, const mcd_opts* opts, mcd_result* total, void* hip_stream);
 
-/* Status and error text. */
+/* ------------------------------------------------------------------ serving
+ *
+ * Requests submitted from any thread are transported by a worker thread of
+ * the context.  Arriving requests wait in a queue (QUEUED) until their device
+ * memory fits the HBM budget (ADMITTED): a batch-statistics tally of 16 x nv
+ * accumulators plus dose and sigma (nv doubles each), so a 256^3 phantom
+ * costs 2.4 GB per request with FP64 sums and 1.3 GB with FP32 sums.  The
+ * worker then runs epochs (RUNNING): one regrouped launch sequence over the
+ * admitted requests of one phantom (phantoms taken in turn), in which every
+ * request advances by a slice of its histories.  Slices are handed out so
+ * that the requests closest to completion finish first and the rest share
+ * the epoch evenly.  A request's histories are the same whatever the slices:
+ * history h always draws from the streams keyed by (seed, request_key, h), so
+ * the result equals mcd_simulate of the same request with the regrouped
+ * kernel up to FP64 summation order.  A request is finalised (dose, sigma,
+ * Dmax, sigma-bar) in the epoch that completes it (DONE) and stays until
+ * mcd_wait collects it.  Not part of the paper, which runs one plan at a time. */
+enum { MCD_QUEUED = 0, MCD_ADMITTED = 1, MCD_RUNNING = 2, MCD_DONE = 3, MCD_FAILED = 4,
+       MCD_CANCELED = 5 };
+
+typedef struct {
+    mcd_opts opts;              /* launch options of the epochs: block_size, grid_blocks,
+                                   stack_depth, chunk_per_lane, regroup, tally_fp32; the
+                                   others must be 0 (kernel: MCD_KERNEL_REGROUPED) */
+    uint64_t epoch_histories;   /* histories per epoch over all its requests, 0 = two cycles'
+                                   worth (2 x lanes x chunk_per_lane) */
+    int32_t max_active;         /* admitted requests at most, 0 = 4096 */
+    int32_t reserved;
+    uint64_t memory_limit;      /* bytes of request memory (tallies, dose, sigma) held at once,
+                                   0 = only the context's HBM budget limits it */
+} mcd_serve_config;
+
+/* Serving counters since the first submit. */
+typedef struct {
+    uint64_t submitted, completed, failed, canceled;
+    uint64_t queued, active;             /* now */
+    uint64_t request_bytes;              /* device memory held by requests now */
+    uint64_t hbm_used, hbm_budget;       /* the context's device memory now, and its cap */
+    uint64_t histories;                  /* histories transported */
+    uint64_t epochs;
+    double busy_ms;                      /* device time of the epochs (set-up to finalisation) */
+    double kernel_ms;                    /* device time of their transport phases */
+    mcd_energy_balance eb;               /* summed over all epochs */
+    uint64_t counters[MCD_NCOUNT];       /* filled when opts.diagnostics */
+} mcd_serve_stats;
+
+/* Sets the serving configuration.  Allowed while no request is queued or
+ * admitted (before the first submit, or once all are collected); else
+ * MCD_E_BUSY.  NULL restores the defaults. */
+int mcd_serve_configure(mcd_ctx* ctx, const mcd_serve_config* cfg);
+
+/* Queues a request (2 <= n_histories < 2^32, seed < 2^32) and returns its
+ * ticket at once; the source is copied.  Never waits for the device.  Starts
+ * the worker thread on first use. */
+int mcd_submit(mcd_ctx* ctx, int32_t phantom, const mcd_source* src, uint64_t n_histories,
+               uint64_t seed, uint32_t request_key, uint64_t* out_ticket);
+
+/* State of a ticket (MCD_QUEUED ... MCD_CANCELED) and histories transported
+ * so far (either pointer may be NULL).  MCD_E_NOTFOUND for an unknown or
+ * already collected ticket. */
+int mcd_poll(mcd_ctx* ctx, uint64_t ticket, int32_t* state, uint64_t* histories_done);
+
+/* Waits up to timeout_ms (< 0: forever) for the request to end.  DONE:
+ * copies dose and sigma into out (as in mcd_simulate; NULL pointers skip),
+ * fills dmax, sigma_bar, kernel_ms (device time of the epochs the request
+ * took part in) and total_ms (submit to completion, wall clock), frees the
+ * request and returns MCD_OK.  FAILED: returns the request's status (the
+ * message in mcd_last_error) and frees it.  CANCELED: MCD_E_CANCELED, freed.
+ * Timeout: MCD_E_BUSY, nothing freed.  eb and counters of a served request
+ * are not kept separately (see mcd_serve_stats). */
+int mcd_wait(mcd_ctx* ctx, uint64_t ticket, mcd_result* out, int64_t timeout_ms);
+
+/* Cancels a request.  A queued request is cancelled at once; an admitted or
+ * running one at the end of the current epoch, when its memory is freed.  A
+ * request that already ended is left as it is.  The ticket is still collected
+ * with mcd_wait. */
+int mcd_cancel(mcd_ctx* ctx, uint64_t ticket);
+
+int mcd_serve_stats_get(mcd_ctx* ctx, mcd_serve_stats* out);
+
+/* Status and error text.  mcd_last_error reports the last failure of a call
+ * made on this context by the calling thread. */
 const char* mcd_status_string(int status);
 const char* mcd_last_error(mcd_ctx* ctx);
 

@@ -149,6 +149,7 @@ __global__ void k_sigma_bar_batches(const FinalReq* reqs, int64_t nv)
 hipError_t launch_finalize_batches(const FinalReq* reqs, int n_req, const uint2* vox,
                                    int64_t nv, double vol, int fp32, hipStream_t s)
 {
+    if (n_req <= 0) return hipSuccess;      // nothing to finalise (e.g. a serving epoch)
     int bx = final_blocks(nv);
     if ((int64_t)bx * n_req > 65536) bx = (int)(65536 / n_req) + 1;
     const dim3 grid(bx, n_req);

@@ -75,10 +75,22 @@ struct RegroupBufs {
     size_t scratch_bytes = 0;
 };
 
+// Per-request overrides of a regrouped run (serving): history offset, seed,
+// persistent tally and dose buffers, and histories already in the tally.
+struct ReqExtra {
+    uint64_t first = 0;
+    uint32_t seed = 0;
+    void* tally = nullptr;
+    double* dose = nullptr;
+    double* sigma = nullptr;
+    const double* nb_prior = nullptr;
+};
+
 // A prepared regrouped run: everything the kernels and the finaliser need.
 struct RegroupPlan {
     int phantom = -1;
     int n_req = 0;
+    int n_fin = 0;                   // requests 0 .. n_fin-1 are finalised after the run
     uint64_t total = 0, chunk = 0;
     int cycles = 0;                  // scheduled cycles
     int blocks = 0, threads = 0;
@@ -94,6 +106,13 @@ struct RegroupPlan {
 }  // namespace mcd
 
 struct mcd_server;
+struct mcd_ctx;
+
+namespace mcd {
+// Uploads the request tables of a plan and runs it on stream s (captured in a
+// graph and replayed when use_graph); returns when the device is done.
+int run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_graph, hipStream_t s);
+}  // namespace mcd
 
 struct mcd_ctx {
     int device = 0;
@@ -101,8 +120,9 @@ struct mcd_ctx {
     int max_lds = 0;     // dynamic LDS bytes a workgroup may use
     hipStream_t stream = nullptr;
     uint64_t budget = 0, used = 0;
-    std::mutex mu;        // tables / phantoms vectors, allocation accounting
-    std::mutex run_mu;    // one blocking run at a time
+    // Lock order: run_mu, then mu, then the server's mutex.
+    std::mutex mu;        // tables / phantoms vectors (changed under run_mu and mu)
+    std::mutex run_mu;    // one device run (blocking call or serving epoch) at a time
     std::mutex mu_alloc;  // budget accounting
     std::vector<mcd::TableSet> tables;
     std::vector<mcd::PhantomRec> phantoms;
@@ -136,8 +156,6 @@ struct mcd_ctx {
     // serving
     mcd_server* server = nullptr;
 
-    std::string last_error;
-
     int fail(int status, const std::string& msg);
     int hip_fail(hipError_t e, const char* what);
     int alloc(void** p, size_t bytes, const char* what);
@@ -154,7 +172,7 @@ struct mcd_ctx {
     // regrouped engine
     int plan_regroup(int32_t phantom, const mcd_source* const* srcs, const uint64_t* ns,
                      const uint32_t* keys, int n_req, uint64_t seed, const mcd_opts* opts,
-                     bool keep_tally, mcd::RegroupPlan& plan);
+                     bool keep_tally, mcd::RegroupPlan& plan, const mcd::ReqExtra* extra = nullptr);
     int enqueue_regroup(const mcd::RegroupPlan& plan, bool clear_tally, hipStream_t s);
     int enqueue_cycles(const mcd::RegroupPlan& plan, int c0, int c1, hipStream_t s);
     int finish_regroup(mcd::RegroupPlan& plan, hipStream_t s, int* cycles_run);
@@ -162,4 +180,6 @@ struct mcd_ctx {
                         hipStream_t s);
     void release_graph();
     void shutdown_serving();
+    bool serving_uses(int32_t phantom);
+    const std::string& last_error() const;
 };

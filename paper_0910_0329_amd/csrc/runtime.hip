@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -33,21 +34,31 @@ const char* mcd_status_string(int status)
     }
 }
 
+// Error messages are kept per calling thread and context, so that the serving
+// worker and the callers of a context do not overwrite each other's.
+static std::string& error_slot(const mcd_ctx* c)
+{
+    thread_local std::map<const mcd_ctx*, std::string> slots;
+    return slots[c];
+}
+
 const char* mcd_last_error(mcd_ctx* ctx)
 {
     if (!ctx) return "null context";
-    return ctx->last_error.c_str();
+    return error_slot(ctx).c_str();
 }
+
+const std::string& mcd_ctx::last_error() const { return error_slot(this); }
 
 int mcd_ctx::fail(int status, const std::string& msg)
 {
-    last_error = msg;
+    error_slot(this) = msg;
     return status;
 }
 
 int mcd_ctx::hip_fail(hipError_t e, const char* what)
 {
-    last_error = std::string(what) + ": " + hipGetErrorString(e);
+    error_slot(this) = std::string(what) + ": " + hipGetErrorString(e);
     return MCD_E_DEVICE;
 }
 
@@ -286,6 +297,7 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
     d.f_e = (float)ts.f_e;
     d.a_hinge = (float)ts.a_hinge;
     ts.live = true;
+    std::lock_guard<std::mutex> run(c->run_mu);
     std::lock_guard<std::mutex> g(c->mu);
     c->tables.push_back(std::move(ts));
     *out_tables = (int32_t)c->tables.size() - 1;
@@ -295,6 +307,7 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
 int mcd_unload_materials(mcd_ctx* c, int32_t t)
 {
     if (!c) return MCD_E_INVAL;
+    std::lock_guard<std::mutex> run(c->run_mu);
     std::lock_guard<std::mutex> g(c->mu);
     if (t < 0 || t >= (int32_t)c->tables.size() || !c->tables[t].live) return MCD_E_NOTFOUND;
     for (auto& p : c->phantoms)
@@ -315,6 +328,7 @@ int mcd_load_phantom(mcd_ctx* c, const mcd_grid* g, const uint8_t* mat, const fl
                      int32_t tables, int32_t* out_phantom)
 {
     if (!c || !g || !mat || !rho || !out_phantom) return MCD_E_INVAL;
+    std::lock_guard<std::mutex> run(c->run_mu);
     if (tables < 0 || tables >= (int32_t)c->tables.size() || !c->tables[tables].live)
         return c->fail(MCD_E_NOTFOUND, "unknown table handle");
     if (g->nx < 1 || g->ny < 1 || g->nz < 1 || !(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0) ||
@@ -377,8 +391,10 @@ int mcd_load_phantom(mcd_ctx* c, const mcd_grid* g, const uint8_t* mat, const fl
 int mcd_unload_phantom(mcd_ctx* c, int32_t ph)
 {
     if (!c) return MCD_E_INVAL;
+    std::lock_guard<std::mutex> run(c->run_mu);
     std::lock_guard<std::mutex> g(c->mu);
     if (ph < 0 || ph >= (int32_t)c->phantoms.size() || !c->phantoms[ph].live) return MCD_E_NOTFOUND;
+    if (c->serving_uses(ph)) return c->fail(MCD_E_BUSY, "phantom has queued or admitted requests");
     PhantomRec& p = c->phantoms[ph];
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();

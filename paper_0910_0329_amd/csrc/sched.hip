@@ -196,7 +196,7 @@ static double batch_count(uint64_t first, uint64_t n, int b)
 
 int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const uint64_t* ns,
                           const uint32_t* keys, int n_req, uint64_t seed, const mcd_opts* opts,
-                          bool keep_tally, RegroupPlan& plan)
+                          bool keep_tally, RegroupPlan& plan, const ReqExtra* extra)
 {
     const PhantomRec& ph = phantoms[phantom];
     if (n_req < 1 || n_req > kMaxBatch) return fail(MCD_E_INVAL, "1 to 4096 requests per launch");
@@ -211,6 +211,7 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
     plan = RegroupPlan();
     plan.phantom = phantom;
     plan.n_req = n_req;
+    plan.n_fin = n_req;
     plan.depth = opts && opts->stack_depth ? opts->stack_depth : kDefaultDepth;
     if (opts && (opts->regroup < 0 || opts->regroup > 2)) return fail(MCD_E_INVAL, "opts: regroup must be 0, 1 or 2");
     plan.use_queues = opts && opts->regroup == 1;
@@ -225,20 +226,21 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
     plan.nb.assign((size_t)n_req * kBatches, 0.0);
     uint64_t lo = 0;
     for (int r = 0; r < n_req; ++r) {
-        if (ns[r] == 0 || ns[r] >= ((uint64_t)1 << 32) || first + ns[r] > ((uint64_t)1 << 32))
+        const uint64_t f = extra ? extra[r].first : first;
+        if (ns[r] == 0 || ns[r] >= ((uint64_t)1 << 32) || f + ns[r] > ((uint64_t)1 << 32))
             return fail(MCD_E_INVAL, "need 1 <= n_histories < 2^32 and first + n <= 2^32 (request " +
                                          std::to_string(r) + ")");
         ReqDev& q = plan.req[r];
         std::memset(&q, 0, sizeof q);
         if ((rc = validate_source(srcs[r], &q.src))) return rc;
-        q.seed = (uint32_t)seed;
+        q.seed = extra ? extra[r].seed : (uint32_t)seed;
         q.key = keys[r];
-        q.first = (uint32_t)first;
+        q.first = (uint32_t)f;
         q.n = (uint32_t)ns[r];
         q.lo = lo;
         q.hist = plan.diag && opts ? opts->history_records : nullptr;
         lo += ns[r];
-        for (int b = 0; b < kBatches; ++b) plan.nb[(size_t)r * kBatches + b] = batch_count(first, ns[r], b);
+        for (int b = 0; b < kBatches; ++b) plan.nb[(size_t)r * kBatches + b] = batch_count(f, ns[r], b);
     }
     if (lo >= ((uint64_t)1 << 40)) return fail(MCD_E_INVAL, "at most 2^40 histories per launch");
     plan.total = lo;
@@ -248,7 +250,7 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
 
     // device buffers
     const size_t elem = plan.fp32 ? sizeof(float) : sizeof(double);
-    const size_t tally_bytes = (size_t)n_req * kBatches * (size_t)ph.nv * elem;
+    const size_t tally_bytes = extra ? 0 : (size_t)n_req * kBatches * (size_t)ph.nv * elem;
     const size_t stage_bytes = (size_t)n_req * (size_t)ph.nv * sizeof(double);
     const unsigned int cap = plan.use_queues ? (unsigned int)std::min<uint64_t>(
         std::max<uint64_t>(3 * plan.chunk, 1 << 16), (uint64_t)1 << 30) : (1u << 12);
@@ -280,10 +282,10 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
         if ((rc = grow((void**)&rb.red, &have, (size_t)n_req * 3 * sizeof(double), "request table"))) return rc;
         rb.req_cap = n_req;
     }
-    if (!keep_tally) {
+    if (!keep_tally && tally_bytes) {
         if ((rc = grow(&rb.tally, &rb.tally_bytes, tally_bytes, "tallies"))) return rc;
     }
-    if (rb.stage_bytes < stage_bytes) {
+    if (!extra && rb.stage_bytes < stage_bytes) {
         (void)hipDeviceSynchronize();
         release(rb.dose, rb.stage_bytes);
         release(rb.sigma, rb.stage_bytes);
@@ -302,16 +304,17 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
         return rc;
 
     for (int r = 0; r < n_req; ++r) {
-        plan.req[r].tally = (char*)rb.tally + (size_t)r * kBatches * ph.nv * elem;
+        plan.req[r].tally = extra ? extra[r].tally : (char*)rb.tally + (size_t)r * kBatches * ph.nv * elem;
         FinalReq& f = plan.fin[r];
         std::memset(&f, 0, sizeof f);
         f.tally = plan.req[r].tally;
-        f.dose = rb.dose + (size_t)r * ph.nv;
-        f.sigma = rb.sigma + (size_t)r * ph.nv;
+        f.dose = extra ? extra[r].dose : rb.dose + (size_t)r * ph.nv;
+        f.sigma = extra ? extra[r].sigma : rb.sigma + (size_t)r * ph.nv;
         f.red = rb.red + 3 * r;
         for (int b = 0; b < kBatches; ++b) {
             f.nb[b] = plan.nb[(size_t)r * kBatches + b];
             if (keep_tally) f.nb[b] += rg_nb[b];
+            if (extra && extra[r].nb_prior) f.nb[b] += extra[r].nb_prior[b];
         }
     }
     return MCD_OK;
@@ -387,7 +390,7 @@ int mcd_ctx::enqueue_regroup(const RegroupPlan& plan, bool clear_tally, hipStrea
     if (rc) return rc;
     e = hipEventRecord(ev[2], s);
     if (e == hipSuccess)
-        e = launch_finalize_batches(rb.fin, plan.n_req, ph.vox, ph.nv, ph.g.dx * ph.g.dy * ph.g.dz,
+        e = launch_finalize_batches(rb.fin, plan.n_fin, ph.vox, ph.nv, ph.g.dx * ph.g.dy * ph.g.dz,
                                     plan.fp32, s);
     if (e == hipSuccess) e = hipEventRecord(ev[3], s);
     if (e != hipSuccess) return hip_fail(e, "finalisation launch");
@@ -417,7 +420,7 @@ int mcd_ctx::finish_regroup(RegroupPlan& plan, hipStream_t s, int* cycles_run)
         e = launch_fill_u32(rb.red, (size_t)plan.n_req * 6, 0u, s);
         if (e == hipSuccess) e = hipEventRecord(ev[2], s);
         if (e == hipSuccess)
-            e = launch_finalize_batches(rb.fin, plan.n_req, ph.vox, ph.nv,
+            e = launch_finalize_batches(rb.fin, plan.n_fin, ph.vox, ph.nv,
                                         ph.g.dx * ph.g.dy * ph.g.dz, plan.fp32, s);
         if (e == hipSuccess) e = hipEventRecord(ev[3], s);
         if (e != hipSuccess) return hip_fail(e, "extra cycles");
@@ -478,7 +481,7 @@ void mcd_ctx::release_graph()
 
 // Uploads the request and finaliser tables, then runs the plan (captured
 // into a graph and replayed when `use_graph` is set).
-static int run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_graph, hipStream_t s)
+int mcd::run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_graph, hipStream_t s)
 {
     // S outputs are written by the finaliser straight from the sub-tallies
     hipError_t e = hipMemcpy(c->rb.req, plan.req.data(), plan.n_req * sizeof(ReqDev), hipMemcpyHostToDevice);
@@ -497,6 +500,7 @@ static int run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use
         };
         add(&plan.phantom, sizeof plan.phantom);
         add(&plan.n_req, sizeof plan.n_req);
+        add(&plan.n_fin, sizeof plan.n_fin);
         add(&plan.total, sizeof plan.total);
         add(&plan.chunk, sizeof plan.chunk);
         add(&plan.cycles, sizeof plan.cycles);

@@ -71,6 +71,23 @@ class BatchItem(C.Structure):
                 ("reserved", C.c_uint32), ("out", C.POINTER(Result))]
 
 
+QUEUED, ADMITTED, RUNNING, DONE, FAILED, CANCELED = range(6)
+STATE_NAMES = ("queued", "admitted", "running", "done", "failed", "canceled")
+
+
+class ServeConfig(C.Structure):
+    _fields_ = [("opts", Opts), ("epoch_histories", C.c_uint64), ("max_active", C.c_int32),
+                ("reserved", C.c_int32), ("memory_limit", C.c_uint64)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+                ("canceled", C.c_uint64), ("queued", C.c_uint64), ("active", C.c_uint64),
+                ("request_bytes", C.c_uint64), ("hbm_used", C.c_uint64), ("hbm_budget", C.c_uint64),
+                ("histories", C.c_uint64), ("epochs", C.c_uint64), ("busy_ms", C.c_double),
+                ("kernel_ms", C.c_double), ("eb", EnergyBalance), ("counters", C.c_uint64 * NCOUNT)]
+
+
 HISTORY_DTYPE = np.dtype([("edep", "<f8"), ("track_e", "<f8"), ("hash", "<u8"),
                           ("n_particles", "<u4"), ("escaped", "<u4")])
 
@@ -101,6 +118,13 @@ def lib():
                                    C.POINTER(Opts), C.POINTER(Result), vp]
         L.mcd_simulate_batch.argtypes = [vp, i32, C.POINTER(BatchItem), i32, C.c_uint64,
                                          C.POINTER(Opts), C.POINTER(Result), vp]
+        L.mcd_serve_configure.argtypes = [vp, C.POINTER(ServeConfig)]
+        L.mcd_submit.argtypes = [vp, i32, C.POINTER(Source), C.c_uint64, C.c_uint64, C.c_uint32,
+                                 C.POINTER(C.c_uint64)]
+        L.mcd_poll.argtypes = [vp, C.c_uint64, C.POINTER(i32), C.POINTER(C.c_uint64)]
+        L.mcd_wait.argtypes = [vp, C.c_uint64, C.POINTER(Result), C.c_int64]
+        L.mcd_cancel.argtypes = [vp, C.c_uint64]
+        L.mcd_serve_stats_get.argtypes = [vp, C.POINTER(ServeStats)]
         L.mcd_status_string.argtypes = [C.c_int]
         L.mcd_status_string.restype = C.c_char_p
         L.mcd_last_error.argtypes = [vp]
@@ -111,7 +135,8 @@ def lib():
 
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_load_materials", "mcd_unload_materials",
             "mcd_load_phantom", "mcd_unload_phantom", "mcd_simulate", "mcd_simulate_batch",
-            "mcd_status_string", "mcd_last_error")
+            "mcd_serve_configure", "mcd_submit", "mcd_poll", "mcd_wait", "mcd_cancel",
+            "mcd_serve_stats_get", "mcd_status_string", "mcd_last_error")
 
 
 def make_source(src) -> Source:
@@ -263,6 +288,58 @@ class Engine:
             d["sigma_bar"] = r.sigma_bar
             outs.append(d)
         return outs, _scalars(tot)
+
+    # ------------------------------------------------------------ serving
+
+    def serve_configure(self, epoch_histories: int = 0, max_active: int = 0, memory_limit: int = 0,
+                        **opts):
+        cfg = ServeConfig()
+        cfg.opts = make_opts(**opts)
+        cfg.epoch_histories = epoch_histories
+        cfg.max_active = max_active
+        cfg.memory_limit = memory_limit
+        self._check(lib().mcd_serve_configure(self._h, C.byref(cfg)), "mcd_serve_configure")
+
+    def submit(self, phantom: int, src, n: int, seed: int, key: int = 0) -> int:
+        """Queues a request; returns its ticket without waiting for the device."""
+        s = make_source(src)
+        t = C.c_uint64()
+        self._check(lib().mcd_submit(self._h, phantom, C.byref(s), n, seed, key, C.byref(t)), "mcd_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        """(state, histories done) of a ticket."""
+        st, done = C.c_int32(), C.c_uint64()
+        self._check(lib().mcd_poll(self._h, ticket, C.byref(st), C.byref(done)), "mcd_poll")
+        return st.value, done.value
+
+    def cancel(self, ticket: int):
+        self._check(lib().mcd_cancel(self._h, ticket), "mcd_cancel")
+
+    def wait(self, ticket: int, *, n_vox: int = None, device_out: bool = True, want_dose: bool = True,
+             timeout_ms: int = -1) -> dict:
+        """Waits for a request and collects dose, sigma, Dmax, sigma-bar,
+        its device time and its latency (submit to completion, ms)."""
+        if want_dose and n_vox is None:
+            raise ValueError("n_vox is required for dose outputs")
+        names = ("dose", "sigma") if want_dose else ()
+        r, bufs, _ = self._outputs(names, n_vox, device_out, None)
+        rc = lib().mcd_wait(self._h, ticket, C.byref(r), timeout_ms)
+        self._check(rc, "mcd_wait")
+        out = dict(bufs)
+        out.update({"dmax": r.dmax, "sigma_bar": r.sigma_bar, "kernel_ms": r.kernel_ms,
+                    "latency_ms": r.total_ms})
+        return out
+
+    def serve_stats(self) -> dict:
+        st = ServeStats()
+        self._check(lib().mcd_serve_stats_get(self._h, C.byref(st)), "mcd_serve_stats_get")
+        d = {k: getattr(st, k) for k, _ in ServeStats._fields_ if k not in ("eb", "counters")}
+        eb = st.eb
+        d["bal"] = {"E_src": eb.e_src, "E_csda": eb.e_csda, "E_local": eb.e_local,
+                    "E_esc": eb.e_esc, "E_miss": eb.e_miss, "track_e": eb.track_e}
+        d["cnt"] = dict(zip(COUNT_NAMES, (int(x) for x in st.counters)))
+        return d
 
 
 def _scalars(r: Result) -> dict:

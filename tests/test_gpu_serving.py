@@ -1,0 +1,219 @@
+"""Serving loop on the GPU: requests submitted concurrently, admitted against a
+memory limit, transported in shared epochs and finalised one by one.
+
+A served request runs the same histories as mcd_simulate of that request
+alone (same seed and request key, regrouped kernel), so its dose and sigma
+agree with the standalone run up to FP64 summation order, whatever the epoch
+slicing and whatever else shared its epochs.  One request is also checked
+against the oracle's group-statistics estimator directly.
+"""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0910_0329_amd.inputs import configs, phantoms, sources
+from paper_0910_0329_amd.inputs.sources import ELECTRON, PHOTON
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    from paper_0910_0329_amd.mcdose import Engine
+    assert torch.cuda.is_available()
+    e = Engine(0)
+    yield e
+    e.close()
+
+
+@pytest.fixture(scope="module")
+def th(eng, blob):
+    return eng.load_materials(blob)
+
+
+@pytest.fixture(scope="module")
+def pool(eng, th):
+    """Two resident phantoms: water-lung-water slabs and a small random field."""
+    a = configs.electron_20mev_wlw(1).phantom
+    b = phantoms.random_field_phantom(24, 0.5, seed=51, nz=20)
+    return [(eng.load_phantom(a, th), a), (eng.load_phantom(b, th), b)]
+
+
+def mix(pool):
+    """(phantom slot, source, n, seed, key) of a mixed set of requests."""
+    (_, a), (_, b) = pool
+    e20 = sources.pencil(ELECTRON, 20.0, *a.centre_xy())
+    g6 = g6mv(b, 4.0)
+    e12 = sources.point_field(ELECTRON, *b.centre_xy(), 100.0, 3.0, 3.0, energy=12.0)
+    return [(0, e20, 3000, 1, 0), (1, g6, 20000, 7, 1), (1, e12, 2500, 7, 2),
+            (0, e20, 777, 9, 3), (1, g6, 50000, 11, 4), (0, e20, 4100, 1, 5)]
+
+
+def g6mv(ph, half):
+    return sources.point_field(PHOTON, *ph.centre_xy(), 100.0, half, half, spectrum=sources.spectrum_6mv())
+
+
+def standalone(eng, pool, item):
+    slot, src, n, seed, key = item
+    pid, ph = pool[slot]
+    return eng.simulate(pid, src, n, seed, key, n_vox=ph.n_vox, regroup=2)
+
+
+def same(a, b, ph):
+    d, s = a["dose"].cpu().numpy(), a["sigma"].cpu().numpy()
+    d0, s0 = b["dose"].cpu().numpy(), b["sigma"].cpu().numpy()
+    dmax = d0.max()
+    assert dmax > 0
+    np.testing.assert_allclose(d, d0, rtol=0, atol=1e-9 * dmax)
+    np.testing.assert_allclose(s, s0, rtol=0, atol=1e-7 * dmax)
+    assert a["dmax"] == pytest.approx(b["dmax"], rel=1e-9)
+    assert a["sigma_bar"] == pytest.approx(b["sigma_bar"], rel=1e-6)
+
+
+def test_served_equals_standalone(eng, pool):
+    """Small epochs (many slices per request), requests of two phantoms."""
+    items = mix(pool)
+    log("case serve mix, epoch_histories=6000")
+    eng.serve_configure(epoch_histories=6000, regroup=2)
+    tickets = [eng.submit(pool[sl][0], src, n, seed, key) for sl, src, n, seed, key in items]
+    outs = [eng.wait(t, n_vox=pool[it[0]][1].n_vox) for t, it in zip(tickets, items)]
+    st = eng.serve_stats()
+    log(f"  epochs {st['epochs']} histories {st['histories']}")
+    assert st["histories"] >= sum(it[2] for it in items)
+    assert st["epochs"] >= 10
+    b = st["bal"]
+    assert abs(b["E_csda"] + b["E_local"] + b["E_esc"] + b["E_miss"] - b["E_src"]) <= 1e-6 * b["E_src"]
+    for o, it in zip(outs, items):
+        ref = standalone(eng, pool, it)
+        same(o, ref, pool[it[0]][1])
+        assert o["latency_ms"] > 0
+
+
+def test_served_matches_oracle(eng, blob, pool):
+    """One served request (split over epochs) against the oracle's estimator."""
+    pid, ph = pool[0]
+    src = sources.pencil(ELECTRON, 20.0, *ph.centre_xy())
+    n = 2000
+    log("case serve e20 vs oracle n=2000")
+    eng.serve_configure(epoch_histories=700, regroup=2)
+    o = eng.wait(eng.submit(pid, src, n, 1, 0), n_vox=ph.n_vox)
+    ref = oracle.simulate(blob, ph, src, n, 1, 0, groups=True)
+    d_ref, s_ref, dmax_ref, _ = oracle.finalize_groups(ph, ref["Sb"], ref["nb"])
+    d, s = o["dose"].cpu().numpy(), o["sigma"].cpu().numpy()
+    sel = d_ref > 0.1 * dmax_ref
+    diff = np.abs(d - d_ref)
+    ok = (diff <= 0.01 * dmax_ref) | (diff <= 2 * np.sqrt(s ** 2 + s_ref ** 2))
+    assert ok[sel].all()
+    assert o["dmax"] == pytest.approx(dmax_ref, rel=0.05)
+
+
+def test_concurrent_submitters(eng, pool):
+    """Requests submitted and collected from several threads."""
+    items = mix(pool)
+    eng.serve_configure(epoch_histories=20000, regroup=2)
+    res = {}
+    errs = []
+
+    def client(i, it):
+        try:
+            sl, src, n, seed, key = it
+            t = eng.submit(pool[sl][0], src, n, seed, key)
+            res[i] = eng.wait(t, n_vox=pool[sl][1].n_vox)
+        except Exception as e:  # pragma: no cover - reported below
+            errs.append(e)
+
+    log("case serve threads=6")
+    ths = [threading.Thread(target=client, args=(i, it)) for i, it in enumerate(items)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join(timeout=120)
+    assert not errs, errs
+    assert len(res) == len(items)
+    for i, it in enumerate(items):
+        same(res[i], standalone(eng, pool, it), pool[it[0]][1])
+
+
+def test_cancel(eng, pool):
+    from paper_0910_0329_amd.mcdose import CANCELED, E_CANCELED, McdError
+    pid, ph = pool[1]
+    g6 = g6mv(ph, 4.0)
+    eng.serve_configure(epoch_histories=50000, max_active=1, regroup=2)
+    log("case serve cancel")
+    big = eng.submit(pid, g6, 50_000_000, 3, 10)         # admitted, runs many epochs
+    queued = eng.submit(pid, g6, 10_000, 3, 11)          # waits behind it (max_active 1)
+    small = eng.submit(pid, g6, 10_000, 3, 12)
+    eng.cancel(queued)
+    assert eng.poll(queued)[0] == CANCELED
+    eng.cancel(big)
+    with pytest.raises(McdError) as ei:
+        eng.wait(big, n_vox=ph.n_vox)
+    assert ei.value.status == E_CANCELED
+    with pytest.raises(McdError):
+        eng.wait(queued, n_vox=ph.n_vox)
+    o = eng.wait(small, n_vox=ph.n_vox)
+    same(o, eng.simulate(pid, g6, 10_000, 3, 12, n_vox=ph.n_vox, regroup=2), ph)
+    st = eng.serve_stats()
+    assert st["queued"] == 0 and st["active"] == 0 and st["request_bytes"] == 0
+
+
+def test_memory_limit_admission(eng, pool, th):
+    """With room for one request at a time every request still completes, and
+    one larger than the limit fails with NOMEM without disturbing the rest."""
+    from paper_0910_0329_amd.mcdose import E_NOMEM, McdError
+    items = mix(pool)
+    nv = max(ph.n_vox for _, ph in pool)
+    one = 16 * nv * 8 + 2 * nv * 8
+    big_ph = phantoms.homogeneous(64, 64, 64, 0.5)
+    big = eng.load_phantom(big_ph, th)
+    eng.serve_configure(epoch_histories=8000, memory_limit=int(1.5 * one), regroup=2)
+    limit = int(1.5 * one)
+    log("case serve memory limit")
+    tickets = [eng.submit(pool[sl][0], src, n, seed, key) for sl, src, n, seed, key in items]
+    tb = eng.submit(big, sources.pencil(ELECTRON, 20.0, *big_ph.centre_xy()), 1000, 1, 99)
+    peak = 0
+    for _ in range(500):
+        st = eng.serve_stats()
+        peak = max(peak, st["request_bytes"])
+        if st["queued"] == 0 and st["active"] == 0:
+            break
+        time.sleep(0.005)
+    assert 0 < peak <= limit
+    for t, it in zip(tickets, items):
+        same(eng.wait(t, n_vox=pool[it[0]][1].n_vox), standalone(eng, pool, it), pool[it[0]][1])
+    with pytest.raises(McdError) as ei:
+        eng.wait(tb, n_vox=big_ph.n_vox)
+    assert ei.value.status == E_NOMEM
+    eng.unload_phantom(big)
+
+
+def test_unload_busy_and_bad_tickets(eng, pool):
+    from paper_0910_0329_amd.mcdose import E_BUSY, E_NOTFOUND, McdError
+    pid, ph = pool[1]
+    g6 = g6mv(ph, 4.0)
+    eng.serve_configure(epoch_histories=50000, regroup=2)
+    t = eng.submit(pid, g6, 2_000_000, 5, 0)
+    with pytest.raises(McdError) as ei:
+        eng.unload_phantom(pid)
+    assert ei.value.status == E_BUSY
+    with pytest.raises(McdError) as ei:
+        eng.serve_configure(epoch_histories=1000)
+    assert ei.value.status == E_BUSY
+    eng.wait(t, n_vox=ph.n_vox)
+    with pytest.raises(McdError) as ei:
+        eng.poll(t)
+    assert ei.value.status == E_NOTFOUND
+    with pytest.raises(McdError):
+        eng.submit(pid, g6, 1, 5, 0)
+    with pytest.raises(McdError):
+        eng.submit(pid + 100, g6, 100, 5, 0)
