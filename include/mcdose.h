@@ -163,6 +163,8 @@ typedef struct {
     double sigma_bar;     /* mean sigma/D over voxels with D > dmax / 2 (Sec. 3) */
     double kernel_ms;     /* device time of the transport kernel(s) */
     double total_ms;      /* device time from tally clear to finalisation */
+    int32_t launches;     /* transport kernel launches of the run */
+    int32_t reserved;
 } mcd_result;
 
 /* Creates a context on HIP device `device`.  hbm_budget_bytes caps what the

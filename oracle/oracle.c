@@ -1019,6 +1019,12 @@ int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n,
 
 /* ---------------------------------------------------------------- finalize */
 
+/* Dmax and sigma-bar are taken over tissue voxels only: density at least
+ * 0.05 g/cm^3 (lung and denser).  The paper's phantoms hold no air; in a
+ * CT-like phantom an air voxel's dose comes from a few deposits in a tiny
+ * mass, so it would set Dmax and dominate sigma-bar with noise. */
+#define ORC_TISSUE_RHO_MIN 0.05f
+
 int orc_finalize(const orc_grid* g, const float* rho, const double* S, const double* Q,
                  uint64_t n, double* dose, double* sigma, double* dmax, double* sigma_bar)
 {
@@ -1033,12 +1039,12 @@ int orc_finalize(const orc_grid* g, const float* rho, const double* S, const dou
         double var = (Q[v] / N - mean * mean) / (N - 1.0);
         dose[v] = mean * scale;
         sigma[v] = sqrt(var > 0.0 ? var : 0.0) * scale;
-        if (dose[v] > mx) mx = dose[v];
+        if (rho[v] >= ORC_TISSUE_RHO_MIN && dose[v] > mx) mx = dose[v];
     }
     double acc = 0.0;
     size_t cntv = 0;
     for (size_t v = 0; v < nv; ++v) {
-        if (dose[v] > 0.5 * mx) {
+        if (rho[v] >= ORC_TISSUE_RHO_MIN && dose[v] > 0.5 * mx) {
             acc += sigma[v] / dose[v];
             ++cntv;
         }
@@ -1082,12 +1088,12 @@ int orc_finalize_groups(const orc_grid* g, const float* rho, const double* Sb, c
         double scale = MEV_PER_G_TO_GY / ((double)rho[v] * vol);
         dose[v] = m * scale;
         sigma[v] = sqrt(var) * scale;
-        if (dose[v] > mx) mx = dose[v];
+        if (rho[v] >= ORC_TISSUE_RHO_MIN && dose[v] > mx) mx = dose[v];
     }
     double acc = 0.0;
     size_t cntv = 0;
     for (size_t v = 0; v < nv; ++v)
-        if (dose[v] > 0.5 * mx) {
+        if (rho[v] >= ORC_TISSUE_RHO_MIN && dose[v] > 0.5 * mx) {
             acc += sigma[v] / dose[v];
             ++cntv;
         }

@@ -1,0 +1,116 @@
+"""Autotuner of the regrouped launch: picks the regrouping schedule, block
+shape and chunk size (which also sizes the particle queues: 3 x lanes x
+chunk_per_lane records) for a workload by timing short batched runs on the
+device, and caches the choice per device and workload shape in a JSON file.
+
+The search times a scaled-down copy of the workload (every item's history
+count divided by `scale`, at least `min_hist`), so a tuning pass costs a few
+seconds; the result depends only on timing, never on the dose, because every
+option runs the same histories.
+"""
+from __future__ import annotations
+
+import hashlib
+import itertools
+import json
+import os
+import time
+
+DEFAULT_SPACE = {
+    "regroup": (1, 2),
+    "chunk_per_lane": (8, 16, 32, 64),
+    "block_size": (256, 512),
+}
+CACHE_ENV = "MCDOSE_TUNE_CACHE"
+
+
+def cache_path() -> str:
+    return os.environ.get(CACHE_ENV) or os.path.join(os.path.expanduser("~"), ".cache", "mcdose_autotune.json")
+
+
+def workload_key(device_name: str, n_vox: int, items) -> str:
+    """Device, phantom size and the mix of sources (particle kinds and the
+    order of magnitude of the history counts)."""
+    kinds = sorted({(int(s.particle), int(s.energy_kind)) for s, _, _ in items})
+    tot = sum(int(n) for _, n, _ in items)
+    mag = len(str(max(tot, 1)))
+    raw = json.dumps([device_name, int(n_vox), kinds, len(items), mag])
+    return hashlib.sha1(raw.encode()).hexdigest()[:16]
+
+
+def load_cache(path: str | None = None) -> dict:
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def store_cache(key: str, entry: dict, path: str | None = None):
+    path = path or cache_path()
+    d = load_cache(path)
+    d[key] = entry
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def candidates(space=None):
+    space = space or DEFAULT_SPACE
+    names = sorted(space)
+    for combo in itertools.product(*(space[n] for n in names)):
+        yield dict(zip(names, combo))
+
+
+def scaled(items, scale: int, min_hist: int):
+    return [(s, max(min_hist, int(n) // scale), k) for s, n, k in items]
+
+
+def tune(eng, phantom: int, n_vox: int, items, seed: int, *, space=None, scale: int = 8,
+         min_hist: int = 2000, reps: int = 2, use_cache: bool = True, path: str | None = None,
+         device_name: str | None = None, log=None) -> dict:
+    """Returns the fastest launch options for `items` (sequence of (source,
+    n_histories, request_key)) on `phantom`, from the cache when present."""
+    import torch
+
+    if device_name is None:
+        p = torch.cuda.get_device_properties(eng.device)
+        device_name = f"{p.name}/{getattr(p, 'gcnArchName', '')}/{p.multi_processor_count}"
+    key = workload_key(device_name, n_vox, items)
+    if use_cache:
+        hit = load_cache(path).get(key)
+        if hit and "opts" in hit:
+            return dict(hit["opts"])
+    probe = scaled(items, scale, min_hist)
+    n_probe = sum(n for _, n, _ in probe)
+    results = []
+    for opts in candidates(space):
+        try:
+            eng.simulate_batch(phantom, probe, seed, n_vox=n_vox, want_dose=False, **opts)   # warm-up
+            best = float("inf")
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                eng.simulate_batch(phantom, probe, seed, n_vox=n_vox, want_dose=False, **opts)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+        except RuntimeError as e:          # e.g. over the HBM budget: not a candidate
+            if log:
+                log(f"autotune: {opts} failed: {e}")
+            continue
+        results.append((best, opts))
+        if log:
+            log(f"autotune: {opts} {n_probe / best:.3e} hist/s")
+    if not results:
+        raise RuntimeError("autotune: no candidate ran")
+    results.sort(key=lambda t: t[0])
+    best_t, best_opts = results[0]
+    entry = {"opts": best_opts, "hist_per_s": n_probe / best_t, "probe_histories": n_probe,
+             "device": device_name, "n_vox": int(n_vox), "n_items": len(items),
+             "table": [{"opts": o, "hist_per_s": n_probe / t} for t, o in results]}
+    store_cache(key, entry, path)
+    return dict(best_opts)

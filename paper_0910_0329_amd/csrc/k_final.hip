@@ -6,6 +6,11 @@
 namespace mcd {
 
 constexpr double kMevPerGToGy = 1.602176634e-10;
+// Dmax and sigma-bar cover tissue voxels only (density >= 0.05 g/cm^3: lung and
+// denser): an air voxel's dose rests on a few deposits in a tiny mass and
+// would set Dmax and dominate sigma-bar with noise.  Dose and sigma are still
+// written for every voxel.
+constexpr float kTissueRhoMin = 0.05f;
 
 #define DEV_INLINE __device__ __forceinline__
 
@@ -40,26 +45,28 @@ __global__ void k_dose(const double* S, const double* Q, const uint2* vox, int64
     double mx = 0.0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
          v += (int64_t)gridDim.x * blockDim.x) {
-        const double scale = kMevPerGToGy / ((double)__uint_as_float(vox[v].x) * vol);
+        const float rho = __uint_as_float(vox[v].x);
+        const double scale = kMevPerGToGy / ((double)rho * vol);
         const double mean = S[v] / N;
         const double var = (Q[v] / N - mean * mean) / (N - 1.0);
         const double d = mean * scale;
         dose[v] = d;
         sigma[v] = sqrt(var > 0.0 ? var : 0.0) * scale;
-        mx = fmax(mx, d);
+        if (rho >= kTissueRhoMin) mx = fmax(mx, d);
     }
     block_max_to(mx, red);
 }
 
 // sigma-bar: mean of sigma/D over voxels with D > Dmax / 2 (red[1] sum, red[2] count).
-__global__ void k_sigma_bar(const double* dose, const double* sigma, int64_t nv, double* red)
+__global__ void k_sigma_bar(const double* dose, const double* sigma, const uint2* vox, int64_t nv,
+                            double* red)
 {
     const double half = 0.5 * red[0];
     double acc = 0.0, cnt = 0.0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
          v += (int64_t)gridDim.x * blockDim.x) {
         const double d = dose[v];
-        if (d > half) {
+        if (d > half && __uint_as_float(vox[v].x) >= kTissueRhoMin) {
             acc += sigma[v] / d;
             cnt += 1.0;
         }
@@ -80,7 +87,7 @@ hipError_t launch_finalize(const double* S, const double* Q, const uint2* vox, i
     const int blocks = final_blocks(nv);
     hipLaunchKernelGGL(k_dose, dim3(blocks), dim3(256), 0, s, S, Q, vox, nv, vol, (double)n, dose,
                        sigma, red);
-    hipLaunchKernelGGL(k_sigma_bar, dim3(blocks), dim3(256), 0, s, dose, sigma, nv, red);
+    hipLaunchKernelGGL(k_sigma_bar, dim3(blocks), dim3(256), 0, s, dose, sigma, vox, nv, red);
     return hipGetLastError();
 }
 
@@ -120,17 +127,18 @@ __global__ void k_dose_batches(const FinalReq* reqs, const uint2* vox, int64_t n
                 ss += r.nb[b] * dm * dm;
             }
         const double var = nz > 1 ? ss / (double)(nz - 1) / N : 0.0;
-        const double scale = kMevPerGToGy / ((double)__uint_as_float(vox[v].x) * vol);
+        const float rho = __uint_as_float(vox[v].x);
+        const double scale = kMevPerGToGy / ((double)rho * vol);
         const double d = m * scale;
         if (r.S) r.S[v] = S;
         if (r.dose) r.dose[v] = d;
         if (r.sigma) r.sigma[v] = sqrt(var) * scale;
-        mx = fmax(mx, d);
+        if (rho >= kTissueRhoMin) mx = fmax(mx, d);
     }
     block_max_to(mx, r.red);
 }
 
-__global__ void k_sigma_bar_batches(const FinalReq* reqs, int64_t nv)
+__global__ void k_sigma_bar_batches(const FinalReq* reqs, const uint2* vox, int64_t nv)
 {
     const FinalReq& r = reqs[blockIdx.y];
     const double half = 0.5 * r.red[0];
@@ -138,7 +146,7 @@ __global__ void k_sigma_bar_batches(const FinalReq* reqs, int64_t nv)
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
          v += (int64_t)gridDim.x * blockDim.x) {
         const double d = r.dose[v];
-        if (d > half) {
+        if (d > half && __uint_as_float(vox[v].x) >= kTissueRhoMin) {
             acc += r.sigma[v] / d;
             cnt += 1.0;
         }
@@ -155,7 +163,7 @@ hipError_t launch_finalize_batches(const FinalReq* reqs, int n_req, const uint2*
     const dim3 grid(bx, n_req);
     if (fp32) hipLaunchKernelGGL(k_dose_batches<float>, grid, dim3(256), 0, s, reqs, vox, nv, vol);
     else hipLaunchKernelGGL(k_dose_batches<double>, grid, dim3(256), 0, s, reqs, vox, nv, vol);
-    hipLaunchKernelGGL(k_sigma_bar_batches, grid, dim3(256), 0, s, reqs, nv);
+    hipLaunchKernelGGL(k_sigma_bar_batches, grid, dim3(256), 0, s, reqs, vox, nv);
     return hipGetLastError();
 }
 

@@ -93,6 +93,7 @@ struct RegroupPlan {
     int n_fin = 0;                   // requests 0 .. n_fin-1 are finalised after the run
     uint64_t total = 0, chunk = 0;
     int cycles = 0;                  // scheduled cycles
+    int launches = 0;                // transport launches actually run
     int blocks = 0, threads = 0;
     int depth = 0;
     int fp32 = 0;

@@ -178,6 +178,7 @@ int mcd_ctx::simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n_h
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ev[1], ev[2]);
     out->kernel_ms = ms;
+    out->launches = 1;
     (void)hipEventElapsedTime(&ms, ev[0], ev[3]);
     out->total_ms = ms;
     return MCD_OK;
@@ -459,12 +460,14 @@ int mcd_ctx::collect_regroup(const RegroupPlan& plan, mcd_result* const* outs, m
         o->dmax = red[3 * r];
         o->sigma_bar = red[3 * r + 2] > 0 ? red[3 * r + 1] / red[3 * r + 2] : 0.0;
         o->kernel_ms = kms;
+        o->launches = plan.launches;
         o->total_ms = tms;
     }
     if (total) {
         total->eb = {bal[0], bal[1], bal[2], bal[3], bal[4], bal[5]};
         std::memcpy(total->counters, host_small + kOffCnt, sizeof total->counters);
         total->kernel_ms = kms;
+        total->launches = plan.launches;
         total->total_ms = tms;
     }
     return MCD_OK;
@@ -537,7 +540,9 @@ int mcd::run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_g
         if (e != hipSuccess) return c->hip_fail(e, "graph launch");
     }
     int cycles_run = 0;
-    return c->finish_regroup(plan, s, &cycles_run);
+    int rc2 = c->finish_regroup(plan, s, &cycles_run);
+    plan.launches = cycles_run * (plan.use_queues ? 2 : 1);
+    return rc2;
 }
 
 // ------------------------------------------------------------------ public

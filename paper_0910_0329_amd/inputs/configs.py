@@ -4,6 +4,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
+import numpy as np
+
 from . import phantoms, sources
 from .sources import ELECTRON, PHOTON
 
@@ -49,3 +51,51 @@ def electron_20mev_point_field(ph, n: int) -> Workload:
     x, y = ph.centre_xy()
     src = sources.point_field(ELECTRON, x, y, 100.0, 5.0, 5.0, energy=20.0)
     return Workload("e20_field", ph, src, n, 1)
+
+
+# ------------------------------------------------------------ serving workload
+
+SERVING_PHANTOMS = ((64, 0.5, 51), (128, 0.25, 52), (256, 0.2, 53))   # (n, voxel cm, field seed)
+
+
+def serving_phantoms(sizes=SERVING_PHANTOMS):
+    """The resident pool of the serving workload: random-field phantoms of
+    64^3 x 0.5 cm, 128^3 x 0.25 cm and 256^3 x 0.2 cm (32, 32 and 51.2 cm)."""
+    return [phantoms.random_field_phantom(n, d, seed=s) for n, d, s in sizes]
+
+
+@dataclass
+class ServeRequest:
+    index: int              # arrival index, also the Philox request key
+    t: float                # arrival time, s
+    phantom: int            # index into the pool
+    particle: int           # PHOTON (6 MV spectrum) or ELECTRON (mono)
+    energy: float           # electron energy, MeV (photons: 0)
+    side: float             # square field side at the surface, cm
+    target: float           # target sigma-bar (0.01 or 0.02)
+
+
+def serving_requests(rate: float = 20.0, duration: float = 60.0, seed: int = 5, n_phantoms: int = 3):
+    """Poisson arrivals (rate per s over `duration` s); each request draws a
+    phantom, a source (6 MV photons or electrons of U(6, 20) MeV), a square
+    field side U(1, 10) cm and a target sigma-bar of 2% or 1%."""
+    times = sources.poisson_arrivals(rate, duration, seed)
+    rng = np.random.default_rng(seed + 1000)
+    out = []
+    for i, t in enumerate(times):
+        ph = int(rng.integers(n_phantoms))
+        particle = PHOTON if rng.random() < 0.5 else ELECTRON
+        energy = float(rng.uniform(6.0, 20.0))
+        side = float(rng.uniform(1.0, 10.0))
+        target = 0.02 if rng.random() < 0.5 else 0.01
+        out.append(ServeRequest(i, float(t), ph, particle, energy if particle == ELECTRON else 0.0, side,
+                                target))
+    return out
+
+
+def serving_source(ph, particle: int, energy: float, side: float) -> sources.Source:
+    """Point source at SSD 100 cm above the centre, square field of `side` cm."""
+    x, y = ph.centre_xy()
+    if particle == PHOTON:
+        return sources.point_field(PHOTON, x, y, 100.0, side / 2, side / 2, spectrum=sources.spectrum_6mv())
+    return sources.point_field(ELECTRON, x, y, 100.0, side / 2, side / 2, energy=energy)

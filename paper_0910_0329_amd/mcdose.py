@@ -63,7 +63,8 @@ class Result(C.Structure):
     _fields_ = [("dose", C.c_void_p), ("sigma", C.c_void_p), ("S", C.c_void_p), ("Q", C.c_void_p),
                 ("on_device", C.c_int32), ("eb", EnergyBalance),
                 ("counters", C.c_uint64 * NCOUNT), ("dmax", C.c_double),
-                ("sigma_bar", C.c_double), ("kernel_ms", C.c_double), ("total_ms", C.c_double)]
+                ("sigma_bar", C.c_double), ("kernel_ms", C.c_double), ("total_ms", C.c_double),
+                ("launches", C.c_int32), ("reserved", C.c_int32)]
 
 
 class BatchItem(C.Structure):
@@ -349,5 +350,5 @@ def _scalars(r: Result) -> dict:
                 "E_esc": eb.e_esc, "E_miss": eb.e_miss, "track_e": eb.track_e},
         "cnt": dict(zip(COUNT_NAMES, (int(x) for x in r.counters))),
         "dmax": r.dmax, "sigma_bar": r.sigma_bar, "kernel_ms": r.kernel_ms,
-        "total_ms": r.total_ms,
+        "total_ms": r.total_ms, "launches": r.launches,
     }

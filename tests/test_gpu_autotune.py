@@ -1,0 +1,38 @@
+"""Autotuner on the GPU: it returns runnable options, caches them, and the
+tuned batch gives the same dose as the default one (the options never change
+which histories run)."""
+import numpy as np
+import pytest
+
+from paper_0910_0329_amd import autotune
+from paper_0910_0329_amd.inputs import configs, sources
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_and_reuse(blob, tmp_path):
+    import torch
+    from paper_0910_0329_amd.mcdose import Engine
+    assert torch.cuda.is_available()
+    eng = Engine(0)
+    try:
+        th = eng.load_materials(blob)
+        w = configs.photon_6mv_wbw(1)
+        pid = eng.load_phantom(w.phantom, th)
+        srcs, ns = sources.beamlets(w.phantom, seed=4)
+        items = [(s, int(n) // 50 + 100, i) for i, (s, n) in enumerate(zip(srcs[:16], ns[:16]))]
+        path = str(tmp_path / "tune.json")
+        space = {"regroup": (1, 2), "chunk_per_lane": (16, 64), "block_size": (512,)}
+        opts = autotune.tune(eng, pid, w.phantom.n_vox, items, 4, space=space, scale=1, reps=1, path=path,
+                             log=print)
+        assert opts in list(autotune.candidates(space))
+        assert autotune.load_cache(path)
+        again = autotune.tune(eng, pid, w.phantom.n_vox, items, 4, space=space, path=path)
+        assert again == opts
+        a, _ = eng.simulate_batch(pid, items, 4, n_vox=w.phantom.n_vox, **opts)
+        b, _ = eng.simulate_batch(pid, items, 4, n_vox=w.phantom.n_vox)
+        for x, y in zip(a, b):
+            d0 = y["dose"].cpu().numpy()
+            np.testing.assert_allclose(x["dose"].cpu().numpy(), d0, rtol=0, atol=1e-9 * d0.max())
+    finally:
+        eng.close()

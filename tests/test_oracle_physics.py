@@ -354,3 +354,28 @@ def test_finalize_hand_example():
     assert dmax == pytest.approx(1.5 * gy)
     # both voxels exceed Dmax/2: mean of sigma/D = (0.408248/1 + 0) / 2
     assert sbar == pytest.approx(0.5 * math.sqrt(0.5 / 3))
+
+
+def test_finalize_ignores_air_for_dmax_and_sigma_bar():
+    """Voxel 2 is air (0.0012 g/cm^3): its dose (S/(N rho V)) is the largest
+    but Dmax and sigma-bar cover tissue voxels (>= 0.05 g/cm^3) only; its dose
+    and sigma are still reported.  Same rule for the group estimator."""
+    rho = np.array([[[1.0, 0.26, 0.0012]]], np.float32)
+    ph = phantoms.Phantom(3, 1, 1, 1.0, 1.0, 1.0, mat=np.zeros((1, 1, 3), np.uint8), rho=rho)
+    S = np.array([4.0, 2.0, 1.0])
+    Q = np.array([6.0, 2.0, 1.0])
+    dose, sigma, dmax, sbar = oracle.finalize(ph, S, Q, 4)
+    gy = 1.602176634e-10
+    assert dose[2] == pytest.approx(0.25 / 0.0012 * gy, rel=1e-6) and sigma[2] > 0
+    assert dmax == pytest.approx(0.5 / 0.26 * gy)          # the lung voxel
+    # tissue voxels above Dmax/2 (0.96 gy-units): lung (1.92) and water (1.0)
+    s_lung = math.sqrt((0.5 - 0.25) / 3) / 0.5
+    s_water = math.sqrt((1.5 - 1.0) / 3) / 1.0
+    assert sbar == pytest.approx(0.5 * (s_lung + s_water))
+    # group estimator: 16 groups of one history each; all deposits in group 0
+    Sb = np.zeros((16, 3))
+    Sb[0] = S
+    nb = np.ones(16)
+    dose_g, _, dmax_g, _ = oracle.finalize_groups(ph, Sb, nb)
+    assert dose_g[2] == pytest.approx(1.0 / 16 / 0.0012 * gy, rel=1e-6)
+    assert dmax_g == pytest.approx(2.0 / 16 / 0.26 * gy)
