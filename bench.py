@@ -42,8 +42,8 @@ sys.path.insert(0, ROOT)
 # of each workload divided by 2e5 (profiles/transport_lockstep_valu.md).  Each
 # VALU instruction of that path is one lane-op of the history's own work.
 PATH_LANE_OPS = {
-    "g6mv_wbw_61x61x60": 4457704078 / 200_000,     # 22288.5
-    "e20_wlw_32x32x30": 17456423285 / 200_000,     # 87282.1
+    "g6mv_wbw_61x61x60": 3633205689 / 200_000,     # 18166.0
+    "e20_wlw_32x32x30": 14025850734 / 200_000,     # 70129.3
 }
 # Plain VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # = 3.93e13 lane-ops/s (one non-packed FP32/INT32 op per lane per cycle).
@@ -52,7 +52,7 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # and WRITE_SIZE, each scaled by its reading for a 1 GiB device copy
 # (profiles/transport_g6mv_hbm_traffic.md).
 TRAFFIC_BYTES_PER_HIST = {
-    "g6mv_wbw_61x61x60": (3391203 * 2.0 + 34340458 * 1.0) * 1024 / 155871405,   # 270.2
+    "g6mv_wbw_61x61x60": (11053001.625 * 2.0 + 34924706.375 * 1.0) * 1024 / 155871405,   # 374.7
 }
 METRIC = "histories/s (6 MV photon, 20 MeV e-) at 1% sigma; p50/p99 dose-request latency"
 

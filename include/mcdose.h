@@ -143,6 +143,16 @@ typedef struct {
                                  secondaries go through the photon/electron queues, 2 = they
                                  stay on the lane's own stack (one lane transports a whole
                                  history; the phases then only split new histories) */
+    /* Wave schedule of both kernels: each iteration a wave runs one kind of
+     * step for the lanes that need it.  Fetching a particle runs when at
+     * least 1/fetch_div of the wave's live lanes need one, sampling hard
+     * events when 1/hard_div wait for it, photon flights when photons are at
+     * least electrons/photon_div; else electron segments.  1..64, 0 = default
+     * (4, 16, 4). */
+    int32_t sched_fetch_div;
+    int32_t sched_hard_div;
+    int32_t sched_photon_div;
+    int32_t reserved0;
 } mcd_opts;
 
 /* Output of a run.  dose and sigma (nx*ny*nz doubles each, Gy per source

@@ -1,7 +1,8 @@
 """Autotuner of the regrouped launch: picks the regrouping schedule, block
 shape and chunk size (which also sizes the particle queues: 3 x lanes x
-chunk_per_lane records) for a workload by timing short batched runs on the
-device, and caches the choice per device and workload shape in a JSON file.
+chunk_per_lane records), then the wave-schedule thresholds, for a workload by
+timing short batched runs on the device, and caches the choice per device and
+workload shape in a JSON file.
 
 The search times a scaled-down copy of the workload (every item's history
 count divided by `scale`, at least `min_hist`), so a tuning pass costs a few
@@ -20,6 +21,12 @@ DEFAULT_SPACE = {
     "regroup": (1, 2),
     "chunk_per_lane": (8, 16, 32, 64),
     "block_size": (256, 512),
+}
+# second stage, searched around the best launch options
+SCHED_SPACE = {
+    "sched_fetch_div": (3, 4, 6),
+    "sched_hard_div": (8, 16, 32),
+    "sched_photon_div": (2, 4),
 }
 CACHE_ENV = "MCDOSE_TUNE_CACHE"
 
@@ -70,11 +77,14 @@ def scaled(items, scale: int, min_hist: int):
     return [(s, max(min_hist, int(n) // scale), k) for s, n, k in items]
 
 
-def tune(eng, phantom: int, n_vox: int, items, seed: int, *, space=None, scale: int = 8,
-         min_hist: int = 2000, reps: int = 2, use_cache: bool = True, path: str | None = None,
-         device_name: str | None = None, log=None) -> dict:
+def tune(eng, phantom: int, n_vox: int, items, seed: int, *, space=None, sched_space=None,
+         scale: int = 8, min_hist: int = 2000, reps: int = 2, use_cache: bool = True,
+         path: str | None = None, device_name: str | None = None, log=None) -> dict:
     """Returns the fastest launch options for `items` (sequence of (source,
-    n_histories, request_key)) on `phantom`, from the cache when present."""
+    n_histories, request_key)) on `phantom`, from the cache when present.
+    Stage 1 searches `space` (launch shape and regrouping); stage 2 searches
+    `sched_space` (wave-schedule thresholds) with the stage-1 winner; an
+    empty `sched_space` ({}) skips stage 2."""
     import torch
 
     if device_name is None:
@@ -88,29 +98,45 @@ def tune(eng, phantom: int, n_vox: int, items, seed: int, *, space=None, scale: 
     probe = scaled(items, scale, min_hist)
     n_probe = sum(n for _, n, _ in probe)
     results = []
-    for opts in candidates(space):
-        try:
-            eng.simulate_batch(phantom, probe, seed, n_vox=n_vox, want_dose=False, **opts)   # warm-up
-            best = float("inf")
-            for _ in range(reps):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                eng.simulate_batch(phantom, probe, seed, n_vox=n_vox, want_dose=False, **opts)
-                torch.cuda.synchronize()
-                best = min(best, time.perf_counter() - t0)
-        except RuntimeError as e:          # e.g. over the HBM budget: not a candidate
-            if log:
-                log(f"autotune: {opts} failed: {e}")
-            continue
-        results.append((best, opts))
-        if log:
-            log(f"autotune: {opts} {n_probe / best:.3e} hist/s")
+    stage2 = SCHED_SPACE if sched_space is None else sched_space
+    trials = list(candidates(space))
+    for opts in trials:
+        results.append(_time(eng, phantom, n_vox, probe, n_probe, seed, opts, reps, log))
+    results = [r for r in results if r]
     if not results:
         raise RuntimeError("autotune: no candidate ran")
     results.sort(key=lambda t: t[0])
+    if stage2:
+        base = results[0][1]
+        for extra in candidates(stage2):
+            r = _time(eng, phantom, n_vox, probe, n_probe, seed, {**base, **extra}, reps, log)
+            if r:
+                results.append(r)
+        results.sort(key=lambda t: t[0])
     best_t, best_opts = results[0]
     entry = {"opts": best_opts, "hist_per_s": n_probe / best_t, "probe_histories": n_probe,
              "device": device_name, "n_vox": int(n_vox), "n_items": len(items),
              "table": [{"opts": o, "hist_per_s": n_probe / t} for t, o in results]}
     store_cache(key, entry, path)
     return dict(best_opts)
+
+
+def _time(eng, phantom, n_vox, probe, n_probe, seed, opts, reps, log):
+    """Best of `reps` timed batched runs after a warm-up; None if it fails."""
+    import torch
+    try:
+        eng.simulate_batch(phantom, probe, seed, n_vox=n_vox, want_dose=False, **opts)   # warm-up
+        best = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eng.simulate_batch(phantom, probe, seed, n_vox=n_vox, want_dose=False, **opts)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+    except RuntimeError as e:          # e.g. over the HBM budget: not a candidate
+        if log:
+            log(f"autotune: {opts} failed: {e}")
+        return None
+    if log:
+        log(f"autotune: {opts} {n_probe / best:.3e} hist/s")
+    return best, dict(opts)

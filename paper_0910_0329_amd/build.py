@@ -28,17 +28,34 @@ HOT_KERNELS = ("_ZN3mcd7k_plainILb0EEEvNS_6KPlainE", "_ZN3mcd7k_phaseILb0ELb1EEE
                "_ZN3mcd7k_phaseILb0ELb0EEEvNS_6KPhaseE")
 
 
-def resource_usage(remarks: str) -> dict:
-    """Per-kernel register/scratch usage from hipcc's kernel-resource-usage remarks."""
+def resource_usage(asm: str) -> dict:
+    """Per-kernel register and scratch figures from the code-object metadata
+    at the end of the device assembly."""
     out, cur = {}, None
-    for line in remarks.splitlines():
-        m = re.search(r"remark: Function Name: (\S+)", line)
+    keys = {"private_segment_fixed_size": "ScratchSize", "sgpr_count": "SGPRs",
+            "sgpr_spill_count": "SGPRsSpill", "vgpr_count": "VGPRs", "vgpr_spill_count": "VGPRsSpill"}
+    for line in asm.splitlines():
+        m = re.match(r"\s+\.name:\s+(\S+)", line)
         if m:
             cur = out.setdefault(m.group(1), {})
             continue
-        m = re.search(r"remark:\s+([A-Za-z ]+?)(?: \[bytes/lane\])?: (\d+)", line)
-        if m and cur is not None:
-            cur[m.group(1).replace(" ", "")] = int(m.group(2))
+        m = re.match(r"\s+\.(\w+):\s+(\d+)\s*$", line)
+        if m and cur is not None and m.group(1) in keys:
+            cur[keys[m.group(1)]] = int(m.group(2))
+    return out
+
+
+def scratch_instructions(asm: str) -> dict:
+    """Private-memory instructions (scratch_*, buffer_*) per kernel in device assembly."""
+    out, cur = {}, None
+    for line in asm.splitlines():
+        m = re.match(r"^(_Z\S+):", line)
+        if m:
+            cur = m.group(1)
+            out.setdefault(cur, 0)
+            continue
+        if cur and re.match(r"\s+(scratch|buffer)_(load|store)", line):
+            out[cur] += 1
     return out
 
 
@@ -53,20 +70,26 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [hipcc(), *HIPCC_FLAGS, "-Rpass-analysis=kernel-resource-usage", "-I", INCLUDE,
-               "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
-        r = subprocess.run(cmd, capture_output=True, text=True)
+        cmd = [hipcc(), *HIPCC_FLAGS, "-save-temps=obj",
+               "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True, cwd=objdir)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
-        usage = resource_usage(r.stderr)
+        asm_path = os.path.join(objdir, src.replace(".hip", "") + "-hip-amdgcn-amd-amdhsa-gfx950.s")
+        with open(asm_path) as f:
+            asm = f.read()
+        usage = resource_usage(asm)
+        priv = scratch_instructions(asm)
         if verbose:
             for k, v in usage.items():
-                print(k, v, file=sys.stderr)
-        for name, u in usage.items():
+                print(k, v, "scratch instructions:", priv.get(k, 0), file=sys.stderr)
+        for name in HOT_KERNELS:
             # the production transport kernels must keep their state in registers:
-            # private scratch in the step loop costs several times the runtime
-            if name in HOT_KERNELS and u.get("ScratchSize", 0) > 0:
-                raise RuntimeError(f"{name} uses {u['ScratchSize']} bytes/lane of private scratch")
+            # private-memory traffic in the step loop costs several times the
+            # runtime (a frame the compiler reserves but never touches is harmless)
+            if priv.get(name, 0) > 0:
+                raise RuntimeError(f"{name} has {priv[name]} private-memory instructions "
+                                   f"({usage.get(name, {}).get('ScratchSize', 0)} bytes/lane)")
         return obj
 
     with ThreadPoolExecutor(len(SOURCES)) as ex:

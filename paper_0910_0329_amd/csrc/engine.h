@@ -40,6 +40,13 @@ struct DevSource {
     double extra;           // 2 m c^2 for positron primaries, else 0
 };
 
+// Wave schedule of the transport loop (thresholds, see Transport::run).
+struct Sched {
+    int fetch_div;           // fetch when >= 1/fetch_div of the live lanes need a particle
+    int hard_div;            // sample hard events when >= 1/hard_div of the live lanes wait
+    int photon_div;          // photon flights when photons >= electrons / photon_div
+};
+
 // Tables and phantom of a launch.
 struct KGeom {
     DevTables t;
@@ -68,6 +75,7 @@ struct KPlain {
     size_t lane_bytes;
     void* hist;              // mcd_history_record[n] or null
     int lockstep;            // 1: all lanes of a wave run the same history
+    Sched sched;
 };
 
 // One request of a regrouped launch (device copy).
@@ -112,6 +120,7 @@ struct KPhase {
     char* scratch;           // per-lane particle stacks
     int stack_depth;
     size_t lane_bytes;
+    Sched sched;
 };
 
 size_t plain_lane_bytes(int stack_depth, int slots);

@@ -25,6 +25,12 @@ struct PlainLane : Transport<PlainLane<DIAG>, DIAG> {
     int sp, nused, lgslots;
     int cur_v;
     float cur_e;
+    // history assignment
+    const float* s_edges;
+    const float* s_cdf;
+    size_t lane_id, n_lanes;
+    uint32_t off, rounds;
+    bool have;
     // per-history diagnostics
     double h_edep, h_track;
     uint64_t h_hash;
@@ -40,6 +46,8 @@ struct PlainLane : Transport<PlainLane<DIAG>, DIAG> {
         lgslots = 31 - __builtin_clz((unsigned)p.slots);
         cur_v = -1;
         cur_e = 0.f;
+        off = rounds = 0;
+        have = false;
         h_edep = h_track = 0.0;
         h_hash = 0;
         h_parts = h_esc = 0;
@@ -117,6 +125,44 @@ struct PlainLane : Transport<PlainLane<DIAG>, DIAG> {
         load_rec(stack + (size_t)sp * kRec, q);
     }
 
+    // Next particle of the lane: the top of its stack, else (after closing
+    // the history it has finished) the source particle of a new history.
+    // False when no work is left.
+    DEV bool fetch(Part& q)
+    {
+        if (sp > 0) {
+            pop(q);
+            this->start_particle(q);
+            return true;
+        }
+        if (have) {
+            finish_history(off);
+            have = false;
+        }
+        // Only the lane's own failure stops it: polling the shared error flag
+        // here costs a system-scope load per history on the critical path
+        // (measured 4x slower); other lanes finish their work and the host
+        // reports the error.
+        if (this->failed) return false;
+        unsigned long long o;
+        if (p.lockstep) {
+            // every lane of a wave takes the same history (a static round-robin
+            // over waves): the wave then runs that history's instruction path
+            // without divergence
+            o = (unsigned long long)(lane_id >> 6) + (unsigned long long)rounds * (n_lanes >> 6);
+            ++rounds;
+        } else {
+            o = atomicAdd(p.next, 1ull);
+        }
+        if (o >= (unsigned long long)p.n) return false;
+        off = (uint32_t)o;
+        have = true;
+        q.h = p.first + off;
+        this->start_history(q, p.src, s_edges, s_cdf);
+        if (q.type != DEAD) this->start_particle(q);
+        return true;
+    }
+
     // Dose collection at history end: S += e_{h,v}, Q += e_{h,v}^2 (FP64).
     DEV void finish_history(uint32_t off)
     {
@@ -149,7 +195,7 @@ struct PlainLane : Transport<PlainLane<DIAG>, DIAG> {
 };
 
 template <bool DIAG>
-__global__ __launch_bounds__(512) void k_plain(KPlain p)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_plain(KPlain p)
 {
     extern __shared__ float4 lds[];
     Env env;
@@ -164,52 +210,18 @@ __global__ __launch_bounds__(512) void k_plain(KPlain p)
     env.key = p.key;
 
     const size_t lane_id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t n_lanes = (size_t)gridDim.x * blockDim.x;
     PlainLane<DIAG> L(p, p.scratch + lane_id * p.lane_bytes);
     L.env = env;
     L.init_base();
+    L.s_edges = s_edges;
+    L.s_cdf = s_cdf;
+    L.lane_id = lane_id;
+    L.n_lanes = (size_t)gridDim.x * blockDim.x;
     Part q;
     q.type = DEAD;
     q.slot = 0;
-    bool have = false;
-    uint32_t off = 0, rounds = 0;
-    for (;;) {
-        if (q.type == DEAD) {
-            if (L.sp > 0) {
-                L.pop(q);
-                L.start_particle(q);
-            } else {
-                if (have) {
-                    L.finish_history(off);
-                    have = false;
-                }
-                // Only the lane's own failure stops it: polling the shared error
-                // flag here costs a system-scope load per history on the
-                // critical path (measured 4x slower); other lanes finish their
-                // work and the host reports the error.
-                if (L.failed) break;
-                unsigned long long o;
-                if (p.lockstep) {
-                    // every lane of a wave takes the same history (a static
-                    // round-robin over waves): the wave then runs that
-                    // history's instruction path without divergence
-                    o = (unsigned long long)(lane_id >> 6) + (unsigned long long)rounds * (n_lanes >> 6);
-                    ++rounds;
-                } else {
-                    o = atomicAdd(p.next, 1ull);
-                }
-                if (o >= (unsigned long long)p.n) break;
-                off = (uint32_t)o;
-                have = true;
-                q.h = p.first + off;
-                L.start_history(q, p.src, s_edges, s_cdf);
-                if (q.type != DEAD) L.start_particle(q);
-                continue;
-            }
-        }
-        L.step(q);
-        if (L.failed) break;
-    }
+    q.pend = 0;
+    L.run(q, p.sched);
     L.reduce_out(p.bal, p.cnt);
 }
 

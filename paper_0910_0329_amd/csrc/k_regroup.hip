@@ -38,6 +38,9 @@ struct PhaseLane : Transport<PhaseLane<DIAG, PHOTONS>, DIAG> {
     uint32_t first;
     // per-particle diagnostics
     double p_edep, p_track;
+    // work sources of this phase
+    unsigned int n_in;
+    bool more_new;
 
     DEV PhaseLane(const KPhase& pp, char* base) : Transport<PhaseLane<DIAG, PHOTONS>, DIAG>(pp.g),
                                                    p(pp), stack(base), sp(0), cur_v(-1), cur_e(0.f),
@@ -148,6 +151,30 @@ struct PhaseLane : Transport<PhaseLane<DIAG, PHOTONS>, DIAG> {
         return true;
     }
 
+    // Next particle of the lane: its own stack, else the input queue, else a
+    // new history of this cycle (photon phase).  False when no work is left.
+    DEV bool fetch(Part& q)
+    {
+        if (sp > 0) {
+            --sp;
+            load_rec(stack + (size_t)sp * kRec, q);
+            return begin(q);
+        }
+        if (n_in) {
+            const unsigned int i = atomicAdd(&p.q_in_ctl->head, 1u);
+            if (i < n_in) {
+                load_rec(p.q_in + (size_t)i * kRec, q);
+                return begin(q);
+            }
+            n_in = 0;
+        }
+        if (more_new && !this->failed) {
+            more_new = claim(q);
+            return more_new;
+        }
+        return false;
+    }
+
     // Claims the next new history of this cycle.  Returns false when none is left.
     DEV bool claim(Part& q)
     {
@@ -177,7 +204,7 @@ struct PhaseLane : Transport<PhaseLane<DIAG, PHOTONS>, DIAG> {
 };
 
 template <bool DIAG, bool PHOTONS>
-__global__ __launch_bounds__(512) void k_phase(KPhase p)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_phase(KPhase p)
 {
     extern __shared__ float4 lds[];
     Env env;
@@ -193,37 +220,12 @@ __global__ __launch_bounds__(512) void k_phase(KPhase p)
     PhaseLane<DIAG, PHOTONS> L(p, p.scratch + lane_id * p.lane_bytes);
     L.env = env;
     L.init_base();
-    const unsigned int n_in = min(p.q_in_ctl->count, p.q_cap);
-    bool more_new = PHOTONS;
+    L.n_in = min(p.q_in_ctl->count, p.q_cap);
+    L.more_new = PHOTONS;
     Part q;
     q.type = DEAD;
-    for (;;) {
-        if (q.type == DEAD) {
-            if (L.sp > 0) {
-                --L.sp;
-                load_rec(L.stack + (size_t)L.sp * kRec, q);
-                if (!L.begin(q)) break;
-            } else {
-                bool got = false;
-                if (n_in) {
-                    const unsigned int i = atomicAdd(&p.q_in_ctl->head, 1u);
-                    if (i < n_in) {
-                        load_rec(p.q_in + (size_t)i * kRec, q);
-                        if (!L.begin(q)) break;
-                        got = true;
-                    }
-                }
-                if (!got && more_new) {
-                    more_new = L.claim(q);
-                    got = more_new;
-                }
-                if (!got || L.failed) break;
-            }
-            continue;
-        }
-        L.step(q);
-        if (L.failed) break;
-    }
+    q.pend = 0;
+    L.run(q, p.sched);
     L.reduce_out(p.bal, p.cnt);
 }
 

@@ -25,6 +25,9 @@ constexpr int kDefaultChunkPerLane = 16;
 constexpr int kLdsPerCu = 160 * 1024;
 constexpr int kTailCycles = 8;      // cycles scheduled after the last new history
 constexpr int kMaxBatch = 4096;
+constexpr int kDefaultFetchDiv = 4;
+constexpr int kDefaultHardDiv = 16;
+constexpr int kDefaultPhotonDiv = 4;
 
 // Small per-run device block: energy balance, counters, error flag, work
 // counter and finalisation reductions of the plain kernel.
@@ -99,6 +102,7 @@ struct RegroupPlan {
     int fp32 = 0;
     bool diag = false;
     bool use_queues = false;
+    Sched sched{};
     std::vector<ReqDev> req;
     std::vector<FinalReq> fin;
     std::vector<double> nb;          // n_req * kBatches histories per sub-tally
@@ -167,6 +171,7 @@ struct mcd_ctx {
     int ensure_tallies(int64_t nv, hipStream_t s);
     int ensure_stage(int64_t nv, hipStream_t s);
     int launch_shape(const mcd_opts* o, int n_mat, int* blocks, int* threads);
+    int wave_schedule(const mcd_opts* o, mcd::Sched* sc);
     void fill_geom(mcd::KGeom& g, const mcd::PhantomRec& ph);
     int simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n, uint64_t seed,
                        uint32_t key, const mcd_opts* opts, mcd_result* out, hipStream_t s);

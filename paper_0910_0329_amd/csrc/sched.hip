@@ -38,6 +38,17 @@ int mcd_ctx::launch_shape(const mcd_opts* o, int n_mat, int* blocks, int* thread
     return MCD_OK;
 }
 
+int mcd_ctx::wave_schedule(const mcd_opts* o, Sched* sc)
+{
+    sc->fetch_div = o && o->sched_fetch_div ? o->sched_fetch_div : kDefaultFetchDiv;
+    sc->hard_div = o && o->sched_hard_div ? o->sched_hard_div : kDefaultHardDiv;
+    sc->photon_div = o && o->sched_photon_div ? o->sched_photon_div : kDefaultPhotonDiv;
+    if (sc->fetch_div < 1 || sc->fetch_div > 64 || sc->hard_div < 1 || sc->hard_div > 64 ||
+        sc->photon_div < 1 || sc->photon_div > 64)
+        return fail(MCD_E_INVAL, "opts: sched_fetch_div, sched_hard_div, sched_photon_div in [0, 64]");
+    return MCD_OK;
+}
+
 void mcd_ctx::fill_geom(KGeom& g, const PhantomRec& ph)
 {
     std::memset(&g, 0, sizeof g);
@@ -85,6 +96,8 @@ int mcd_ctx::simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n_h
     int blocks, threads;
     rc = launch_shape(opts, tables[ph.tables].n_mat, &blocks, &threads);
     if (rc) return rc;
+    Sched sc;
+    if ((rc = wave_schedule(opts, &sc))) return rc;
     const bool diag = opts && opts->diagnostics;
     const bool accumulate = opts && opts->accumulate;
     if (opts && opts->history_records && !diag)
@@ -118,6 +131,7 @@ int mcd_ctx::simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n_h
     p.lane_bytes = lane_bytes;
     p.hist = diag && opts ? opts->history_records : nullptr;
     p.lockstep = opts && opts->lockstep ? 1 : 0;
+    p.sched = sc;
     double* red = (double*)(small + kOffRed);
 
     hipError_t e = hipEventRecord(ev[0], s);
@@ -222,6 +236,7 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
         return fail(MCD_E_INVAL, "history records need diagnostics and a single request");
     int rc = launch_shape(opts, tables[ph.tables].n_mat, &plan.blocks, &plan.threads);
     if (rc) return rc;
+    if ((rc = wave_schedule(opts, &plan.sched))) return rc;
     plan.req.resize(n_req);
     plan.fin.resize(n_req);
     plan.nb.assign((size_t)n_req * kBatches, 0.0);
@@ -342,6 +357,7 @@ int mcd_ctx::enqueue_cycles(const RegroupPlan& plan, int c0, int c1, hipStream_t
     k.scratch = rb.scratch;
     k.stack_depth = plan.depth;
     k.lane_bytes = phase_lane_bytes(plan.depth);
+    k.sched = plan.sched;
     char* Qg[2] = {rb.queues, rb.queues + (size_t)rb.cap * kRec};
     char* Qe[2] = {rb.queues + (size_t)2 * rb.cap * kRec, rb.queues + (size_t)3 * rb.cap * kRec};
     QCtl* Cg[2] = {rb.ctl + 0, rb.ctl + 1};
@@ -512,6 +528,7 @@ int mcd::run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_g
         add(&plan.depth, sizeof plan.depth);
         add(&plan.fp32, sizeof plan.fp32);
         add(&plan.diag, sizeof plan.diag);
+        add(&plan.sched, sizeof plan.sched);
         add(&clear_tally, sizeof clear_tally);
         add(&c->rb, sizeof c->rb);
         add(&c->small, sizeof c->small);

@@ -73,6 +73,7 @@ struct Part {
     int ix, iy, iz;          // electron voxel (state, advanced across faces)
     float nh, xi, kap;       // hard-event mfps to go, hinge fraction, hinge budget
     int before;              // 1 before the hinge of the current step
+    int pend;                // 1: the segment ended at a hard event not yet sampled
 };
 
 // Particle record in a stack or queue: 48 bytes.
@@ -101,6 +102,7 @@ DEV void load_rec(const char* base, Part& q)
     q.d = __float_as_uint(c.w);
     q.g = q.d >> 2;
     q.nsp = 0;
+    q.pend = 0;
 }
 
 // Read-only view of tables staged in LDS plus the phantom geometry.
@@ -322,6 +324,7 @@ struct Transport {
     // source): an electron is born with its hard-event mfps and hinge position.
     DEV void start_particle(Part& q)
     {
+        q.pend = 0;
         if (DIAG) p_hash = (0xcbf29ce484222325ull ^ ((uint64_t)q.l1 << 32 | q.l0)) * 0x100000001b3ull;
         if (q.type != PHOTON) {
             floor_voxel(q.x, q.y, q.z, q.ix, q.iy, q.iz);
@@ -350,6 +353,7 @@ struct Transport {
         q.d = 0;
         q.g = 0;
         q.nsp = 0;
+        q.pend = 0;
         const float u0 = uni(q), u1 = uni(q), u2 = uni(q), u3 = uni(q);
         float e;
         if (s.energy_kind == MCD_MONO) {
@@ -576,7 +580,7 @@ struct Transport {
             if (q.type == POSITRON) annihilate(q, q.x, q.y, q.z, vx);
             end_particle(q);
         } else if (lim == LIM_H) {
-            hard_event(q, m, vx);
+            q.pend = 1;                   // sampled by hard_event when the wave runs them
         } else if (lim == LIM_K) {
             if (q.before) {
                 count(MCD_C_HINGES);
@@ -615,9 +619,15 @@ struct Transport {
         }
     }
 
-    DEV void hard_event(Part& q, int m, int vx)
+    // The hard event that ended the last segment of q (Moller or
+    // bremsstrahlung, chosen by their cross sections at T), then the number
+    // of mean free paths to the next one.
+    DEV void hard_event(Part& q)
     {
         const KGeom& g = G();
+        q.pend = 0;
+        const int vx = lin(q.ix, q.iy, q.iz);
+        const int m = (int)g.vox[vx].y;
         float T = q.e;
         int i;
         float fr;
@@ -676,10 +686,50 @@ struct Transport {
         q.nh = neg_ln(uni(q));
     }
 
-    DEV void step(Part& q)
+    // ---------------------------------------------------- wave schedule
+    // Each lane holds one particle in one of four states: it needs a new
+    // particle (FETCH), it is a photon (PHOTON), an electron or positron
+    // (ELECTRON), or its last segment ended at a hard event (HARD).  Every
+    // iteration the wave picks one kind of work from the lanes' states and
+    // only the lanes in that state run it, so the wave runs one code path with
+    // as many lanes as it can: the rare, long paths (fetching a particle,
+    // which includes starting and closing histories, and sampling a hard
+    // event) wait until a share of the live lanes need them (1/fetch_div and
+    // 1/hard_div), and photons run when they are at least 1/photon_div of the
+    // electrons.  A lane's own particle and stream never change: only the
+    // time at which its steps run.  Returns when the lane's fetch finds no
+    // more work, or on failure.
+    enum { ST_FETCH, ST_PHOTON, ST_ELECTRON, ST_HARD };
+
+    DEV void run(Part& q, const Sched sc)
     {
-        if (q.type == PHOTON) photon_step(q);
-        else electron_step(q);
+        for (;;) {
+            const int st = q.type == DEAD ? ST_FETCH
+                         : (q.type == PHOTON ? ST_PHOTON : (q.pend ? ST_HARD : ST_ELECTRON));
+            const int n = __popcll(__builtin_amdgcn_ballot_w64(true));
+            const int nf = __popcll(__builtin_amdgcn_ballot_w64(st == ST_FETCH));
+            const int np = __popcll(__builtin_amdgcn_ballot_w64(st == ST_PHOTON));
+            const int nh = __popcll(__builtin_amdgcn_ballot_w64(st == ST_HARD));
+            const int ne = n - nf - np - nh;
+            int act;
+            if (nf && (nf * sc.fetch_div >= n || nf == n)) act = ST_FETCH;
+            else if (nh && (nh * sc.hard_div >= n || nh + nf == n)) act = ST_HARD;
+            else if (np && np * sc.photon_div >= ne) act = ST_PHOTON;
+            else if (ne) act = ST_ELECTRON;
+            else act = nh ? ST_HARD : ST_FETCH;
+            if (st == act) {
+                if (act == ST_FETCH) {
+                    if (!self().fetch(q)) break;
+                } else if (act == ST_PHOTON) {
+                    photon_step(q);
+                } else if (act == ST_ELECTRON) {
+                    electron_step(q);
+                } else {
+                    hard_event(q);
+                }
+            }
+            if (failed) break;
+        }
     }
 
     // Wave-level reduction of the energy balance and counters, one atomic per wave.

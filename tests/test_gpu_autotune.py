@@ -23,9 +23,11 @@ def test_tune_and_reuse(blob, tmp_path):
         items = [(s, int(n) // 50 + 100, i) for i, (s, n) in enumerate(zip(srcs[:16], ns[:16]))]
         path = str(tmp_path / "tune.json")
         space = {"regroup": (1, 2), "chunk_per_lane": (16, 64), "block_size": (512,)}
-        opts = autotune.tune(eng, pid, w.phantom.n_vox, items, 4, space=space, scale=1, reps=1, path=path,
-                             log=print)
-        assert opts in list(autotune.candidates(space))
+        sched = {"sched_fetch_div": (3, 4), "sched_hard_div": (16,), "sched_photon_div": (4,)}
+        opts = autotune.tune(eng, pid, w.phantom.n_vox, items, 4, space=space, sched_space=sched, scale=1,
+                             reps=1, path=path, log=print)
+        launch = {k: v for k, v in opts.items() if not k.startswith("sched_")}
+        assert launch in list(autotune.candidates(space))
         assert autotune.load_cache(path)
         again = autotune.tune(eng, pid, w.phantom.n_vox, items, 4, space=space, path=path)
         assert again == opts
