@@ -96,7 +96,13 @@ enum {
     MCD_C_SEGMENTS, MCD_C_SEG_E, MCD_C_SEG_H, MCD_C_SEG_K, MCD_C_SEG_B, MCD_C_SEG_F,
     MCD_C_HINGES, MCD_C_MOLLER, MCD_C_BREMS, MCD_C_SPAWNS, MCD_C_PHILOX, MCD_C_FLUSHES,
     MCD_C_ESCAPES, MCD_C_MISSES, MCD_C_LOCAL, MCD_C_VOID, MCD_C_COMPTON_TRIES,
-    MCD_C_MOLLER_TRIES, MCD_C_MAX_STACK, MCD_NCOUNT = 32
+    MCD_C_MOLLER_TRIES, MCD_C_MAX_STACK,
+    /* wave schedule: iterations of the transport loop (summed over waves),
+     * live lanes summed over them, and per kind of work (fetch, photon flight,
+     * electron segment, hard event) the iterations that ran it and the lanes
+     * that took part */
+    MCD_C_ITERS, MCD_C_LIVE, MCD_C_IT_FETCH, MCD_C_IT_PHOTON, MCD_C_IT_ELECTRON, MCD_C_IT_HARD,
+    MCD_C_LN_FETCH, MCD_C_LN_PHOTON, MCD_C_LN_ELECTRON, MCD_C_LN_HARD, MCD_NCOUNT = 40
 };
 
 /* Per-history diagnostic record (mcd_opts.history_records). */
@@ -136,7 +142,8 @@ typedef struct {
                                  path without divergence; tallies then count each history 64 times */
     int32_t kernel;           /* MCD_KERNEL_REGROUPED (default) or MCD_KERNEL_PLAIN */
     int32_t tally_fp32;       /* regrouped kernel: FP32 instead of FP64 dose accumulators */
-    int32_t chunk_per_lane;   /* regrouped kernel: new histories per lane and cycle, 0 = 16 */
+    int32_t chunk_per_lane;   /* regrouped kernel with queues (regroup 1): new histories per lane
+                                 and cycle, 0 = 16; with lane stacks one launch takes them all */
     int32_t use_graph;        /* regrouped kernel: capture the launch sequence in a hipGraph
                                  and replay it when the same call is repeated */
     int32_t regroup;          /* regrouped kernel schedule: 0 = default, 1 = cross-type

@@ -25,8 +25,8 @@ DEFAULT_SPACE = {
 # second stage, searched around the best launch options
 SCHED_SPACE = {
     "sched_fetch_div": (3, 4, 6),
-    "sched_hard_div": (8, 16, 32),
-    "sched_photon_div": (2, 4),
+    "sched_hard_div": (16, 32),
+    "sched_photon_div": (4, 8),
 }
 CACHE_ENV = "MCDOSE_TUNE_CACHE"
 
@@ -67,10 +67,15 @@ def store_cache(key: str, entry: dict, path: str | None = None):
 
 
 def candidates(space=None):
+    """Every combination of the values in `space`; chunk_per_lane only matters
+    with queues (regroup 1), so lane-stack candidates keep its first value."""
     space = space or DEFAULT_SPACE
     names = sorted(space)
     for combo in itertools.product(*(space[n] for n in names)):
-        yield dict(zip(names, combo))
+        d = dict(zip(names, combo))
+        if d.get("regroup") == 2 and "chunk_per_lane" in space and d["chunk_per_lane"] != space["chunk_per_lane"][0]:
+            continue
+        yield d
 
 
 def scaled(items, scale: int, min_hist: int):

@@ -9,7 +9,7 @@ namespace mcd {
 
 constexpr int kNE = 512;          // energy nodes of every table
 constexpr int kMaxMat = 8;        // materials per table set on the device
-constexpr int kCounters = 32;
+constexpr int kCounters = 40;
 constexpr int kBal = 6;           // e_src, e_csda, e_local, e_esc, e_miss, track_e
 constexpr int kRec = 48;          // bytes per stacked or queued particle
 constexpr int kBatches = 16;      // sub-tallies of the batch-statistics tally (power of two)

@@ -152,7 +152,7 @@ struct PlainLane : Transport<PlainLane<DIAG>, DIAG> {
             o = (unsigned long long)(lane_id >> 6) + (unsigned long long)rounds * (n_lanes >> 6);
             ++rounds;
         } else {
-            o = atomicAdd(p.next, 1ull);
+            o = wave_fetch_add(p.next);
         }
         if (o >= (unsigned long long)p.n) return false;
         off = (uint32_t)o;

@@ -130,7 +130,7 @@ struct PhaseLane : Transport<PhaseLane<DIAG, PHOTONS>, DIAG> {
     {
         const bool cross = PHOTONS ? s.type != PHOTON : s.type == PHOTON;
         if (cross && p.use_queues) {
-            const unsigned int i = atomicAdd(&p.q_out_ctl->count, 1u);
+            const unsigned int i = wave_fetch_add(&p.q_out_ctl->count);
             if (i < p.q_cap) {
                 store_rec(p.q_out + (size_t)i * kRec, s);
                 return;
@@ -161,7 +161,7 @@ struct PhaseLane : Transport<PhaseLane<DIAG, PHOTONS>, DIAG> {
             return begin(q);
         }
         if (n_in) {
-            const unsigned int i = atomicAdd(&p.q_in_ctl->head, 1u);
+            const unsigned int i = wave_fetch_add(&p.q_in_ctl->head);
             if (i < n_in) {
                 load_rec(p.q_in + (size_t)i * kRec, q);
                 return begin(q);
@@ -178,7 +178,7 @@ struct PhaseLane : Transport<PhaseLane<DIAG, PHOTONS>, DIAG> {
     // Claims the next new history of this cycle.  Returns false when none is left.
     DEV bool claim(Part& q)
     {
-        const unsigned int j = atomicAdd(&p.claim[p.cycle], 1u);
+        const unsigned int j = wave_fetch_add(&p.claim[p.cycle]);
         const uint64_t gi = (uint64_t)p.cycle * p.chunk + j;
         if ((uint64_t)j >= p.chunk || gi >= p.total) return false;
         int lo = 0, hi = p.n_req - 1;          // last request whose first index <= gi

@@ -31,12 +31,14 @@ constexpr int kDefaultPhotonDiv = 4;
 
 // Small per-run device block: energy balance, counters, error flag, work
 // counter and finalisation reductions of the plain kernel.
-constexpr size_t kOffBal = 0;       // kBal doubles
-constexpr size_t kOffCnt = 64;      // kCounters u64
-constexpr size_t kOffErr = 320;     // int
-constexpr size_t kOffNext = 328;    // u64
-constexpr size_t kOffRed = 336;     // 3 doubles: Dmax bits, sum sigma/D, count
-constexpr size_t kSmallBytes = 384;
+constexpr size_t kOffBal = 0;                            // kBal doubles
+constexpr size_t kOffCnt = 64;                           // kCounters u64
+constexpr size_t kOffErr = kOffCnt + 8 * kCounters;      // int
+constexpr size_t kOffNext = kOffErr + 8;                 // u64
+constexpr size_t kOffRed = kOffNext + 8;                 // 3 doubles: Dmax bits, sum sigma/D, count
+constexpr size_t kSmallBytes = (kOffRed + 24 + 63) / 64 * 64;
+static_assert(kOffCnt >= 8 * kBal, "energy balance overlaps the counters");
+static_assert(kSmallBytes % 64 == 0 && kOffRed + 24 <= kSmallBytes, "small block layout");
 
 struct TableSet {
     DevTables dev{};

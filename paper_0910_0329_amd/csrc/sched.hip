@@ -261,7 +261,11 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
     if (lo >= ((uint64_t)1 << 40)) return fail(MCD_E_INVAL, "at most 2^40 histories per launch");
     plan.total = lo;
     const uint64_t lanes = (uint64_t)plan.blocks * plan.threads;
-    plan.chunk = std::min<uint64_t>(lanes * (uint64_t)cpl, plan.total);
+    // With queues a cycle hands the other phase its particles, so new histories
+    // come in chunks; with lane stacks one launch takes every history (each
+    // launch ends with a tail of lanes finishing their last history).
+    plan.chunk = plan.use_queues ? std::min<uint64_t>(lanes * (uint64_t)cpl, plan.total)
+                                 : std::min<uint64_t>(plan.total, (uint64_t)1 << 31);
     plan.cycles = (int)((plan.total + plan.chunk - 1) / plan.chunk) + (plan.use_queues ? kTailCycles : 0);
 
     // device buffers

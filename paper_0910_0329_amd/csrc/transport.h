@@ -36,6 +36,30 @@ enum { EV_VIRTUAL = 1, EV_COMPTON, EV_PHOTO, EV_PAIR, EV_PAIR_VOID, EV_G_ESCAPE,
        EV_SEG = 10, EV_MOLLER = 20, EV_BREMS, EV_MOLLER_VOID, EV_E_ESCAPE };
 
 DEV float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// Wave-aggregated counter increment: the active lanes that reach it share one
+// atomic add of their count on *ctr; each gets old + (its rank among them).
+DEV unsigned int wave_fetch_add(unsigned int* ctr)
+{
+    const uint64_t m = __builtin_amdgcn_ballot_w64(true);
+    const unsigned int rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    unsigned int base = 0;
+    if (rank == 0) base = atomicAdd(ctr, (unsigned int)__popcll(m));
+    return __builtin_amdgcn_readfirstlane(base) + rank;
+}
+
+DEV unsigned long long wave_fetch_add(unsigned long long* ctr)
+{
+    const uint64_t m = __builtin_amdgcn_ballot_w64(true);
+    const unsigned int rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    unsigned long long base = 0;
+    if (rank == 0) base = atomicAdd(ctr, (unsigned long long)__popcll(m));
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+    return ((unsigned long long)hi << 32 | lo) + rank;
+}
 DEV float neg_ln(float u) { return -__log2f(u) * kLn2; }
 
 // Philox4x32-10 (Salmon et al., SC'11), in place on the counter.
@@ -706,7 +730,8 @@ struct Transport {
         for (;;) {
             const int st = q.type == DEAD ? ST_FETCH
                          : (q.type == PHOTON ? ST_PHOTON : (q.pend ? ST_HARD : ST_ELECTRON));
-            const int n = __popcll(__builtin_amdgcn_ballot_w64(true));
+            const uint64_t live = __builtin_amdgcn_ballot_w64(true);
+            const int n = __popcll(live);
             const int nf = __popcll(__builtin_amdgcn_ballot_w64(st == ST_FETCH));
             const int np = __popcll(__builtin_amdgcn_ballot_w64(st == ST_PHOTON));
             const int nh = __popcll(__builtin_amdgcn_ballot_w64(st == ST_HARD));
@@ -717,6 +742,14 @@ struct Transport {
             else if (np && np * sc.photon_div >= ne) act = ST_PHOTON;
             else if (ne) act = ST_ELECTRON;
             else act = nh ? ST_HARD : ST_FETCH;
+            if (DIAG && __builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0u)) == 0) {
+                const int na = act == ST_FETCH ? nf : act == ST_PHOTON ? np : act == ST_ELECTRON ? ne : nh;
+                ++c[MCD_C_ITERS];
+                c[MCD_C_LIVE] += (uint32_t)n;
+                ++c[MCD_C_IT_FETCH + act];
+                c[MCD_C_LN_FETCH + act] += (uint32_t)na;
+            }
             if (st == act) {
                 if (act == ST_FETCH) {
                     if (!self().fetch(q)) break;

@@ -16,11 +16,12 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmcdose.so")
 
 OK, E_INVAL, E_NOMEM, E_NOTFOUND, E_OVERFLOW, E_DEVICE, E_BUSY, E_CANCELED = 0, -1, -2, -3, -4, -5, -6, -7
-NCOUNT = 32
+NCOUNT = 40
 COUNT_NAMES = ("histories", "flights", "virtual", "compton", "photo", "pair", "segments",
                "seg_E", "seg_h", "seg_k", "seg_b", "seg_f", "hinges", "moller", "brems",
                "spawns", "philox", "flushes", "escapes", "misses", "local", "void",
-               "compton_tries", "moller_tries", "max_stack")
+               "compton_tries", "moller_tries", "max_stack", "iters", "live", "it_fetch", "it_photon",
+               "it_electron", "it_hard", "ln_fetch", "ln_photon", "ln_electron", "ln_hard")
 
 
 class McdError(RuntimeError):

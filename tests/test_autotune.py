@@ -12,7 +12,7 @@ def items():
 
 def test_candidates_cover_the_space():
     c = list(autotune.candidates())
-    assert len(c) == 2 * 4 * 2
+    assert len(c) == (4 + 1) * 2          # chunk sizes only with queues (regroup 1)
     assert len({tuple(sorted(d.items())) for d in c}) == len(c)
     assert {"regroup", "chunk_per_lane", "block_size"} == set(c[0])
 
