@@ -27,6 +27,7 @@ struct DevTables {
     float dl2;              // log2 step of the grid
     float emin, emax;
     float e_abs_e, e_abs_g, w_cc, w_cr, kappa_step, f_e, a_hinge;
+    float f_shift;          // log2(1 - f_e) / (log2 step): (1 - f_e) E is this many nodes below E
 };
 
 // Source descriptor as the kernels see it.

@@ -295,6 +295,7 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
     d.w_cr = (float)ts.w_cr;
     d.kappa_step = (float)ts.kappa_step;
     d.f_e = (float)ts.f_e;
+    d.f_shift = (float)(std::log2(1.0 - ts.f_e) * (kNE - 1) / std::log2(ts.emax / ts.emin));
     d.a_hinge = (float)ts.a_hinge;
     ts.live = true;
     std::lock_guard<std::mutex> run(c->run_mu);

@@ -179,10 +179,19 @@ struct Transport {
         count(MCD_C_PHILOX);
     }
 
-    // Keeps at least five uniforms ahead; called once at the start of a step.
+    // Called once at the start of a step.  The ring can take the next block
+    // once the lane draws from its newest block (at most four uniforms left).
+    // The Philox rounds run when some active lane has fewer than two
+    // uniforms left, the most a flight, a segment or a particle start draws
+    // outside the rejection loops; every lane with a free slot then refills
+    // at the same time, so the rounds run for many lanes at once instead of
+    // for a few lanes at almost every step.  Draws beyond the ring refill
+    // in uni().
     DEV void prefetch(Part& q)
     {
-        if ((q.d >> 2) + 1u >= q.g) refill(q);
+        const bool slot = (q.d >> 2) + 1u >= q.g;
+        const bool need = 4u * q.g - q.d < 2u;
+        if (__builtin_amdgcn_ballot_w64(need) != 0 && slot) refill(q);
     }
 
     DEV float uni(Part& q)
@@ -207,23 +216,21 @@ struct Transport {
     }
 
     // ------------------------------------------------------------ tables
-    DEV void eidx(float e, int& i, float& fr) const
+    // Position of energy e on the grid in node units (e clamped to the grid).
+    DEV float epos(float e) const
     {
         const DevTables& t = G().t;
         e = fminf(fmaxf(e, t.emin), t.emax);
-        const float x = (__log2f(e) - t.l2_emin) * t.inv_dl2;
+        return (__log2f(e) - t.l2_emin) * t.inv_dl2;
+    }
+
+    DEV static void node(float x, int& i, float& fr)
+    {
         i = min(max((int)x, 0), kNE - 2);
         fr = x - (float)i;
     }
 
-    DEV float range_at(int m, float e) const
-    {
-        int i;
-        float fr;
-        eidx(e, i, fr);
-        const float a = env.elec[m * kNE + i].x, b = env.elec[m * kNE + i + 1].x;
-        return a + (b - a) * fr;
-    }
+    DEV void eidx(float e, int& i, float& fr) const { node(epos(e), i, fr); }
 
     // Inverse of the interpolated range of material m: the node interval holding
     // r is found by walking down from interval i0 (r does not exceed the range
@@ -561,9 +568,10 @@ struct Transport {
         const float irho = __builtin_amdgcn_rcpf(rho);
         const int m = (int)vd.y;
         const float T = q.e;
+        const float xt = epos(T);
         int i;
         float fr;
-        eidx(T, i, fr);
+        node(xt, i, fr);
         const float4 a = env.elec[m * kNE + i], b = env.elec[m * kNE + i + 1];
         const float rt = a.x + (b.x - a.x) * fr;
         const float lam = a.y + (b.y - a.y) * fr;
@@ -578,7 +586,13 @@ struct Transport {
         int axis;
         const float l_b = boundary(q, axis);
         if (l_b < l) { l = l_b; lim = LIM_B; }
-        const float l_f = (rt - range_at(m, (1.f - g.t.f_e) * T)) * irho;
+        // R((1 - f_E) T): on the log-uniform grid that energy lies a fixed
+        // number of nodes below T
+        int jf;
+        float ff;
+        node(xt + g.t.f_shift, jf, ff);
+        const float rf0 = env.elec[m * kNE + jf].x, rf1 = env.elec[m * kNE + jf + 1].x;
+        const float l_f = (rt - (rf0 + (rf1 - rf0) * ff)) * irho;
         if (l_f < l) { l = l_f; lim = LIM_F; }
         // move and lose energy continuously
         q.x += l * q.u;
