@@ -42,8 +42,8 @@ sys.path.insert(0, ROOT)
 # of each workload divided by 2e5 (profiles/transport_lockstep_valu.md).  Each
 # VALU instruction of that path is one lane-op of the history's own work.
 PATH_LANE_OPS = {
-    "g6mv_wbw_61x61x60": 3633205689 / 200_000,     # 18166.0
-    "e20_wlw_32x32x30": 14025850734 / 200_000,     # 70129.3
+    "g6mv_wbw_61x61x60": 3583582636 / 200_000,     # 17917.9
+    "e20_wlw_32x32x30": 13838920783 / 200_000,     # 69194.6
 }
 # Plain VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # = 3.93e13 lane-ops/s (one non-packed FP32/INT32 op per lane per cycle).
@@ -52,9 +52,17 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # and WRITE_SIZE, each scaled by its reading for a 1 GiB device copy
 # (profiles/transport_g6mv_hbm_traffic.md).
 TRAFFIC_BYTES_PER_HIST = {
-    "g6mv_wbw_61x61x60": (11053001.625 * 2.0 + 34924706.375 * 1.0) * 1024 / 155871405,   # 374.7
+    "g6mv_wbw_61x61x60": (10902741.4375 * 2.0 + 34752195.9375 * 1.0) * 1024 / 155871405,   # 371.6
 }
 METRIC = "histories/s (6 MV photon, 20 MeV e-) at 1% sigma; p50/p99 dose-request latency"
+# The paper's Table 1 (Tesla C1060, FP32; DPM physics and a measured 6 MV
+# spectrum, neither available here): histories, GPU seconds, sigma-bar.
+PAPER_TABLE1 = {
+    "paper_e20_wlw_61x61x150": (10_000_000, 80.6, 0.0065),
+    "paper_e20_wbw_61x61x150": (10_000_000, 101.8, 0.0063),
+    "paper_g6mv_wlw_61x61x150": (1_000_000_000, 845.8, 0.0052),
+    "paper_g6mv_wbw_61x61x150": (1_000_000_000, 1242.3, 0.0046),
+}
 
 
 def parse():
@@ -227,6 +235,22 @@ def main():
         f"10x10 field N_1%={n1f} at {n1f / tf:.3e} hist/s")
     line["electron_20MeV"] = electron
 
+    # ------------------------------------------------------------ paper geometry
+    from paper_0910_0329_amd.inputs.sources import ELECTRON, PHOTON
+    paper = {}
+    for particle in (ELECTRON, PHOTON):
+        for middle in ("lung", "bone"):
+            wp = configs.paper_workload(particle, middle, 0)
+            n_p, t_c1060, sb_c1060 = PAPER_TABLE1[wp.name]
+            pp = eng.load_phantom(wp.phantom, th)
+            tp_, rp_ = timed(lambda: eng.simulate(pp, wp.source, n_p, wp.seed, n_vox=wp.phantom.n_vox), 1)
+            paper[wp.name] = {"histories": n_p, "s": tp_, "hist_per_s": n_p / tp_,
+                              "kernel_hist_per_s": n_p / (rp_["kernel_ms"] * 1e-3), "sigma_bar": rp_["sigma_bar"],
+                              "c1060_s": t_c1060, "c1060_sigma_bar": sb_c1060}
+            eng.unload_phantom(pp)
+            log(f"{wp.name}: {n_p} histories in {tp_:.2f} s (C1060: {t_c1060} s), sigma-bar {rp_['sigma_bar']:.4f}")
+    line["paper_geometry"] = paper
+
     # ------------------------------------------------------------ batched
     from paper_0910_0329_amd import autotune
     srcs, ns = sources.beamlets(wg.phantom, seed=4)
@@ -268,6 +292,10 @@ def main():
         forms["served"] = sv
         log(f"served: p50 {sv['p50_ms']:.0f} ms p99 {sv['p99_ms']:.0f} ms, {sv['hist_per_s']:.3e} hist/s "
             f"(offered {sv['offered_hist_per_s']:.3e})")
+        sa = serving.replay(eng, pool_ids, pool, reqs, cal, seed=5, collectors=32, adaptive=True, log=log)
+        sa["workload"] = "the same arrivals; each request stops at its own sigma-bar target (at most 5e7 histories)"
+        forms["served_adaptive"] = sa
+        log(f"served adaptive: p50 {sa['p50_ms']:.0f} ms p99 {sa['p99_ms']:.0f} ms, {sa['hist_per_s']:.3e} hist/s")
     line["forms"] = forms
 
     # ------------------------------------------------------------ CPU oracle

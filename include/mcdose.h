@@ -182,6 +182,7 @@ typedef struct {
     double total_ms;      /* device time from tally clear to finalisation */
     int32_t launches;     /* transport kernel launches of the run */
     int32_t reserved;
+    uint64_t n_histories; /* histories behind dose and sigma */
 } mcd_result;
 
 /* Creates a context on HIP device `device`.  hbm_budget_bytes caps what the
@@ -290,6 +291,16 @@ int mcd_serve_configure(mcd_ctx* ctx, const mcd_serve_config* cfg);
  * the worker thread on first use. */
 int mcd_submit(mcd_ctx* ctx, int32_t phantom, const mcd_source* src, uint64_t n_histories,
                uint64_t seed, uint32_t request_key, uint64_t* out_ticket);
+
+/* Queues a request that stops at a target uncertainty: its histories run in
+ * epochs as for mcd_submit, and after every epoch it took part in the
+ * request is finalised; it completes once sigma-bar <= sigma_bar_target (and
+ * Dmax > 0, at least 1000 histories) or when n_max histories have run.  The
+ * result equals mcd_simulate of the same request with N = the histories it
+ * ran (mcd_result.n_histories), up to FP64 summation order.
+ * 0 < sigma_bar_target < 1, 1000 <= n_max < 2^32. */
+int mcd_submit_adaptive(mcd_ctx* ctx, int32_t phantom, const mcd_source* src, double sigma_bar_target,
+                        uint64_t n_max, uint64_t seed, uint32_t request_key, uint64_t* out_ticket);
 
 /* State of a ticket (MCD_QUEUED ... MCD_CANCELED) and histories transported
  * so far (either pointer may be NULL).  MCD_E_NOTFOUND for an unknown or

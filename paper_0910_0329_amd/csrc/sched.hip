@@ -193,6 +193,7 @@ int mcd_ctx::simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n_h
     (void)hipEventElapsedTime(&ms, ev[1], ev[2]);
     out->kernel_ms = ms;
     out->launches = 1;
+    out->n_histories = n_total;
     (void)hipEventElapsedTime(&ms, ev[0], ev[3]);
     out->total_ms = ms;
     return MCD_OK;
@@ -481,6 +482,9 @@ int mcd_ctx::collect_regroup(const RegroupPlan& plan, mcd_result* const* outs, m
         o->sigma_bar = red[3 * r + 2] > 0 ? red[3 * r + 1] / red[3 * r + 2] : 0.0;
         o->kernel_ms = kms;
         o->launches = plan.launches;
+        double nh = 0.0;
+        for (int b = 0; b < kBatches; ++b) nh += plan.fin[r].nb[b];
+        o->n_histories = (uint64_t)nh;
         o->total_ms = tms;
     }
     if (total) {
@@ -488,6 +492,7 @@ int mcd_ctx::collect_regroup(const RegroupPlan& plan, mcd_result* const* outs, m
         std::memcpy(total->counters, host_small + kOffCnt, sizeof total->counters);
         total->kernel_ms = kms;
         total->launches = plan.launches;
+        total->n_histories = plan.total;
         total->total_ms = tms;
     }
     return MCD_OK;

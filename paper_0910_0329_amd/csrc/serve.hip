@@ -36,7 +36,8 @@ struct Request {
     uint64_t ticket = 0;
     int32_t phantom = -1;
     mcd_source src{};
-    uint64_t n = 0, done = 0;
+    uint64_t n = 0, done = 0;          // n: histories to run (adaptive: at most)
+    double target = 0.0;               // adaptive: sigma-bar to reach (0: run all n)
     uint32_t seed = 0, key = 0;
     int state = MCD_QUEUED;
     int status = MCD_OK;
@@ -53,6 +54,8 @@ struct Request {
     double dmax = 0, sigma_bar = 0, kernel_ms = 0;
     Clock::time_point t_submit, t_done;
 };
+
+constexpr uint64_t kAdaptiveMin = 1000;   // histories before an adaptive request may stop
 
 double ms_between(Clock::time_point a, Clock::time_point b)
 {
@@ -260,11 +263,13 @@ static void run_epoch(mcd_ctx* c, mcd_server* S)
         slice[i] = std::min(batch[i]->n - batch[i]->done, share);
         left -= std::min(left, slice[i]);
     }
-    // finishing requests first: they are the ones finalised
+    // requests finalised after the epoch first: those that finish, and the
+    // adaptive ones (their sigma-bar decides whether they finish)
     std::vector<size_t> order(n);
     for (size_t i = 0; i < n; ++i) order[i] = i;
-    std::stable_partition(order.begin(), order.end(),
-                          [&](size_t i) { return batch[i]->done + slice[i] == batch[i]->n; });
+    std::stable_partition(order.begin(), order.end(), [&](size_t i) {
+        return batch[i]->done + slice[i] == batch[i]->n || batch[i]->target > 0.0;
+    });
     std::vector<const mcd_source*> srcs(n);
     std::vector<uint64_t> ns(n);
     std::vector<uint32_t> keys(n);
@@ -283,7 +288,7 @@ static void run_epoch(mcd_ctx* c, mcd_server* S)
         extra[j].dose = r->dose;
         extra[j].sigma = r->sigma;
         extra[j].nb_prior = r->nb;
-        if (r->done + ns[j] == r->n) ++n_fin;
+        if (r->done + ns[j] == r->n || r->target > 0.0) ++n_fin;
     }
     mcd_opts o = S->cfg.opts;
     RegroupPlan plan;
@@ -319,7 +324,18 @@ static void run_epoch(mcd_ctx* c, mcd_server* S)
         for (Request* r : rq) end_request(S, r, MCD_FAILED, rc, "serving epoch: " + why);
         return;
     }
-    for (int j = 0; j < n_fin; ++j) free_request_memory(c, rq[j], false);
+    // which requests end with this epoch: all their histories ran, or the
+    // adaptive ones reached their sigma-bar (only the worker writes done and n)
+    std::vector<char> ends(n, 0);
+    for (int j = 0; j < n_fin; ++j) {
+        const Request* r = rq[j];
+        const uint64_t d = r->done + ns[j];
+        const double dmax = red[3 * j];
+        const double sb = red[3 * j + 2] > 0 ? red[3 * j + 1] / red[3 * j + 2] : 0.0;
+        ends[j] = d == r->n || (r->target > 0.0 && d >= kAdaptiveMin && dmax > 0.0 && sb <= r->target);
+    }
+    for (int j = 0; j < n_fin; ++j)
+        if (ends[j]) free_request_memory(c, rq[j], false);
     std::lock_guard<std::mutex> g(S->mu);
     double bal[kBal];
     std::memcpy(bal, small + kOffBal, sizeof bal);
@@ -347,10 +363,9 @@ static void run_epoch(mcd_ctx* c, mcd_server* S)
         if ((int)j < n_fin) {
             r->dmax = red[3 * j];
             r->sigma_bar = red[3 * j + 2] > 0 ? red[3 * j + 1] / red[3 * j + 2] : 0.0;
-            end_request(S, r, MCD_DONE, MCD_OK, "");
-        } else {
-            r->state = MCD_ADMITTED;
         }
+        if (ends[j]) end_request(S, r, MCD_DONE, MCD_OK, "");
+        else r->state = MCD_ADMITTED;
     }
     std::vector<Request*> keep;
     for (Request* r : S->active)
@@ -419,12 +434,9 @@ int mcd_serve_configure(mcd_ctx* c, const mcd_serve_config* cfg)
     return MCD_OK;
 }
 
-int mcd_submit(mcd_ctx* c, int32_t phantom, const mcd_source* src, uint64_t n_histories,
-               uint64_t seed, uint32_t request_key, uint64_t* out_ticket)
+static int submit(mcd_ctx* c, int32_t phantom, const mcd_source* src, uint64_t n_histories, double target,
+                  uint64_t seed, uint32_t request_key, uint64_t* out_ticket)
 {
-    if (!c || !src || !out_ticket) return MCD_E_INVAL;
-    if (n_histories < 2 || n_histories >= ((uint64_t)1 << 32) || seed >= ((uint64_t)1 << 32))
-        return c->fail(MCD_E_INVAL, "need 2 <= n_histories < 2^32 and seed < 2^32");
     DevSource ds;
     int rc = c->validate_source(src, &ds);
     if (rc) return rc;
@@ -440,6 +452,7 @@ int mcd_submit(mcd_ctx* c, int32_t phantom, const mcd_source* src, uint64_t n_hi
     r->phantom = phantom;
     r->src = *src;
     r->n = n_histories;
+    r->target = target;
     r->seed = (uint32_t)seed;
     r->key = request_key;
     r->t_submit = Clock::now();
@@ -465,6 +478,26 @@ int mcd_submit(mcd_ctx* c, int32_t phantom, const mcd_source* src, uint64_t n_hi
     ++S->stats.submitted;
     S->cv_work.notify_one();
     return MCD_OK;
+}
+
+int mcd_submit(mcd_ctx* c, int32_t phantom, const mcd_source* src, uint64_t n_histories,
+               uint64_t seed, uint32_t request_key, uint64_t* out_ticket)
+{
+    if (!c || !src || !out_ticket) return MCD_E_INVAL;
+    if (n_histories < 2 || n_histories >= ((uint64_t)1 << 32) || seed >= ((uint64_t)1 << 32))
+        return c->fail(MCD_E_INVAL, "need 2 <= n_histories < 2^32 and seed < 2^32");
+    return submit(c, phantom, src, n_histories, 0.0, seed, request_key, out_ticket);
+}
+
+int mcd_submit_adaptive(mcd_ctx* c, int32_t phantom, const mcd_source* src, double sigma_bar_target,
+                        uint64_t n_max, uint64_t seed, uint32_t request_key, uint64_t* out_ticket)
+{
+    if (!c || !src || !out_ticket) return MCD_E_INVAL;
+    if (!(sigma_bar_target > 0.0 && sigma_bar_target < 1.0))
+        return c->fail(MCD_E_INVAL, "need 0 < sigma_bar_target < 1");
+    if (n_max < kAdaptiveMin || n_max >= ((uint64_t)1 << 32) || seed >= ((uint64_t)1 << 32))
+        return c->fail(MCD_E_INVAL, "need 1000 <= n_max < 2^32 and seed < 2^32");
+    return submit(c, phantom, src, n_max, sigma_bar_target, seed, request_key, out_ticket);
 }
 
 int mcd_poll(mcd_ctx* c, uint64_t ticket, int32_t* state, uint64_t* histories_done)
@@ -536,6 +569,7 @@ int mcd_wait(mcd_ctx* c, uint64_t ticket, mcd_result* out, int64_t timeout_ms)
         out->sigma_bar = r->sigma_bar;
         out->kernel_ms = r->kernel_ms;
         out->total_ms = ms_between(r->t_submit, r->t_done);
+        out->n_histories = r->done;
     } else if (rc != MCD_OK) {
         c->fail(rc, r->msg);
     }

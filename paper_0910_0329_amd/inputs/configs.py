@@ -99,3 +99,27 @@ def serving_source(ph, particle: int, energy: float, side: float) -> sources.Sou
     if particle == PHOTON:
         return sources.point_field(PHOTON, x, y, 100.0, side / 2, side / 2, spectrum=sources.spectrum_6mv())
     return sources.point_field(ELECTRON, x, y, 100.0, side / 2, side / 2, energy=energy)
+
+
+# ------------------------------------------------ the paper's own geometry
+
+PAPER_SSD = 90.0       # cm, source to phantom surface
+PAPER_SAD = 100.0      # cm, where the 10x10 cm field is defined
+
+
+def paper_workload(particle: int, middle: str, n: int) -> Workload:
+    """The paper's benchmark geometry (Sec. 3, Table 1) on the synthetic
+    physics: 61x61x150 voxels of 0.5x0.5x0.2 cm with 5 cm water, 5 cm lung or
+    bone and 20 cm water; a point source at SSD 90 cm whose 10x10 cm field is
+    defined at SAD 100 cm (9x9 cm on the surface); 20 MeV electrons or the
+    6 MV spectrum.  Seeds: 6 (electrons), 7 (photons)."""
+    ph = phantoms.paper_slab_phantom(middle)
+    x, y = ph.centre_xy()
+    half = 5.0 * PAPER_SSD / PAPER_SAD
+    if particle == PHOTON:
+        src = sources.point_field(PHOTON, x, y, PAPER_SSD, half, half, spectrum=sources.spectrum_6mv())
+        name, seed = f"paper_g6mv_w{middle[0]}w_61x61x150", 7
+    else:
+        src = sources.point_field(ELECTRON, x, y, PAPER_SSD, half, half, energy=20.0)
+        name, seed = f"paper_e20_w{middle[0]}w_61x61x150", 6
+    return Workload(name, ph, src, n, seed)

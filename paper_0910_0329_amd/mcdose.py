@@ -67,7 +67,7 @@ class Result(C.Structure):
                 ("on_device", C.c_int32), ("eb", EnergyBalance),
                 ("counters", C.c_uint64 * NCOUNT), ("dmax", C.c_double),
                 ("sigma_bar", C.c_double), ("kernel_ms", C.c_double), ("total_ms", C.c_double),
-                ("launches", C.c_int32), ("reserved", C.c_int32)]
+                ("launches", C.c_int32), ("reserved", C.c_int32), ("n_histories", C.c_uint64)]
 
 
 class BatchItem(C.Structure):
@@ -125,6 +125,8 @@ def lib():
         L.mcd_serve_configure.argtypes = [vp, C.POINTER(ServeConfig)]
         L.mcd_submit.argtypes = [vp, i32, C.POINTER(Source), C.c_uint64, C.c_uint64, C.c_uint32,
                                  C.POINTER(C.c_uint64)]
+        L.mcd_submit_adaptive.argtypes = [vp, i32, C.POINTER(Source), C.c_double, C.c_uint64, C.c_uint64,
+                                          C.c_uint32, C.POINTER(C.c_uint64)]
         L.mcd_poll.argtypes = [vp, C.c_uint64, C.POINTER(i32), C.POINTER(C.c_uint64)]
         L.mcd_wait.argtypes = [vp, C.c_uint64, C.POINTER(Result), C.c_int64]
         L.mcd_cancel.argtypes = [vp, C.c_uint64]
@@ -139,7 +141,7 @@ def lib():
 
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_load_materials", "mcd_unload_materials",
             "mcd_load_phantom", "mcd_unload_phantom", "mcd_simulate", "mcd_simulate_batch",
-            "mcd_serve_configure", "mcd_submit", "mcd_poll", "mcd_wait", "mcd_cancel",
+            "mcd_serve_configure", "mcd_submit", "mcd_submit_adaptive", "mcd_poll", "mcd_wait", "mcd_cancel",
             "mcd_serve_stats_get", "mcd_status_string", "mcd_last_error")
 
 
@@ -304,11 +306,17 @@ class Engine:
         cfg.memory_limit = memory_limit
         self._check(lib().mcd_serve_configure(self._h, C.byref(cfg)), "mcd_serve_configure")
 
-    def submit(self, phantom: int, src, n: int, seed: int, key: int = 0) -> int:
-        """Queues a request; returns its ticket without waiting for the device."""
+    def submit(self, phantom: int, src, n: int, seed: int, key: int = 0, *, sigma_target: float = None) -> int:
+        """Queues a request; returns its ticket without waiting for the device.
+        With sigma_target the request stops once sigma-bar reaches it (n is
+        then the most histories it may run)."""
         s = make_source(src)
         t = C.c_uint64()
-        self._check(lib().mcd_submit(self._h, phantom, C.byref(s), n, seed, key, C.byref(t)), "mcd_submit")
+        if sigma_target is None:
+            self._check(lib().mcd_submit(self._h, phantom, C.byref(s), n, seed, key, C.byref(t)), "mcd_submit")
+        else:
+            self._check(lib().mcd_submit_adaptive(self._h, phantom, C.byref(s), sigma_target, n, seed, key,
+                                                  C.byref(t)), "mcd_submit_adaptive")
         return t.value
 
     def poll(self, ticket: int):
@@ -332,7 +340,7 @@ class Engine:
         self._check(rc, "mcd_wait")
         out = dict(bufs)
         out.update({"dmax": r.dmax, "sigma_bar": r.sigma_bar, "kernel_ms": r.kernel_ms,
-                    "latency_ms": r.total_ms})
+                    "latency_ms": r.total_ms, "n_histories": r.n_histories})
         return out
 
     def serve_stats(self) -> dict:
@@ -353,5 +361,5 @@ def _scalars(r: Result) -> dict:
                 "E_esc": eb.e_esc, "E_miss": eb.e_miss, "track_e": eb.track_e},
         "cnt": dict(zip(COUNT_NAMES, (int(x) for x in r.counters))),
         "dmax": r.dmax, "sigma_bar": r.sigma_bar, "kernel_ms": r.kernel_ms,
-        "total_ms": r.total_ms, "launches": r.launches,
+        "total_ms": r.total_ms, "launches": r.launches, "n_histories": r.n_histories,
     }

@@ -58,14 +58,16 @@ def n_histories(cal, req, clip=(100_000, 50_000_000)) -> int:
 
 
 def replay(eng, pool_ids, pool, reqs, cal, seed=5, clip=(100_000, 50_000_000), collectors=8,
-           log=None) -> dict:
+           adaptive=False, log=None) -> dict:
     """Submits every request at its arrival time (relative to the start of the
-    replay) and collects the results on `collectors` threads."""
+    replay) and collects the results on `collectors` threads.  adaptive: each
+    request runs until its own sigma-bar reaches the target (at most the
+    clipped upper bound), instead of the calibrated history count."""
     tickets = queue.Queue()
     done = []
     failures = []
     lock = threading.Lock()
-    plan = [(r, n_histories(cal, r, clip)) for r in reqs]
+    plan = [(r, clip[1] if adaptive else n_histories(cal, r, clip)) for r in reqs]
 
     def collect():
         while True:
@@ -75,6 +77,7 @@ def replay(eng, pool_ids, pool, reqs, cal, seed=5, clip=(100_000, 50_000_000), c
             r, n, t, t_sub = item
             try:
                 out = eng.wait(t, want_dose=False)
+                n = out["n_histories"]
             except RuntimeError as e:
                 with lock:
                     failures.append((r.index, str(e)))
@@ -96,7 +99,7 @@ def replay(eng, pool_ids, pool, reqs, cal, seed=5, clip=(100_000, 50_000_000), c
             time.sleep(delay)
         src = configs.serving_source(pool[r.phantom], r.particle, r.energy, r.side)
         t_sub = time.perf_counter() - t0
-        t = eng.submit(pool_ids[r.phantom], src, n, seed, r.index)
+        t = eng.submit(pool_ids[r.phantom], src, n, seed, r.index, sigma_target=r.target if adaptive else None)
         tickets.put((r, n, t, t_sub))
     t_last_submit = time.perf_counter() - t0
     if log:
@@ -109,7 +112,7 @@ def replay(eng, pool_ids, pool, reqs, cal, seed=5, clip=(100_000, 50_000_000), c
     lat = np.array([d["latency_ms"] for d in done]) if done else np.zeros(1)
     makespan = max([d["done_s"] for d in done] + [t_last_submit])
     hist = sum(d["n"] for d in done)
-    offered = sum(n for _, n in plan)
+    offered = sum(n for _, n in plan) if not adaptive else sum(d["n"] for d in done)
     duration = max(r.t for r in reqs) if reqs else 0.0
     ach = np.array([d["sigma_bar"] / d["target"] for d in done if d["sigma_bar"] > 0])
     busy = s1["busy_ms"] - s0["busy_ms"]

@@ -90,7 +90,11 @@ def check_balance(g, ref):
     closed = b["E_csda"] + b["E_local"] + b["E_esc"] + b["E_miss"]
     assert abs(closed - b["E_src"]) <= 1e-6 * b["E_src"]
     S = g["S"].cpu().numpy()
-    assert S.sum() == pytest.approx(b["E_csda"] + b["E_local"], rel=1e-9)
+    # S sums per-history (plain) or per-visit (regrouped) FP32 partial sums in
+    # FP64, the balance sums every deposit in FP64: each partial sum of k
+    # deposits carries at most (k - 1) 2^-24 relative rounding, so with k of
+    # order ten the two totals agree to 1e-6 (the balance bar), not to FP64.
+    assert S.sum() == pytest.approx(b["E_csda"] + b["E_local"], rel=1e-6)
     assert b["E_src"] == pytest.approx(ref["bal"]["E_src"], rel=1e-6)
 
 
@@ -139,6 +143,21 @@ def test_random_field_phantom_all_particles(eng, blob, th, particle, e, kernel):
     log(f"case rf particle={particle} e={e} n={n} kernel={kernel}")
     g, ref = run_both(eng, blob, th, ph, src, n, seed=9, key=3, kernel=kernel)
     check_dose(ph, g, ref, n, kernel)
+    check_balance(g, ref)
+    f = match_fraction(g, ref)
+    log(f"  history match fraction {f:.4f}")
+    assert f > 0.8
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("particle,middle,n", [(ELECTRON, "lung", 4_000), (PHOTON, "bone", 60_000)])
+def test_paper_geometry(eng, blob, th, particle, middle, n, kernel):
+    """The paper's benchmark geometry (Sec. 3): 61x61x150 voxels of 0.5x0.5x0.2 cm,
+    5/5/20 cm slabs, point source at SSD 90 cm with the 10x10 cm field at SAD 100."""
+    w = configs.paper_workload(particle, middle, n)
+    log(f"case {w.name} n={n} kernel={kernel}")
+    g, ref = run_both(eng, blob, th, w.phantom, w.source, n, w.seed, kernel=kernel)
+    check_dose(w.phantom, g, ref, n, kernel)
     check_balance(g, ref)
     f = match_fraction(g, ref)
     log(f"  history match fraction {f:.4f}")

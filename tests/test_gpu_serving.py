@@ -217,3 +217,33 @@ def test_unload_busy_and_bad_tickets(eng, pool):
         eng.submit(pid, g6, 1, 5, 0)
     with pytest.raises(McdError):
         eng.submit(pid + 100, g6, 100, 5, 0)
+
+
+def test_adaptive_stop_equals_fixed_run(eng, pool):
+    """A request with a sigma-bar target stops after the epoch that reaches it;
+    its result equals the fixed-N run with the histories it ran."""
+    pid, ph = pool[0]
+    src = sources.pencil(ELECTRON, 20.0, *ph.centre_xy())
+    eng.serve_configure(epoch_histories=1500, regroup=2)
+    log("case serve adaptive target 3%")
+    t = eng.submit(pid, src, 1_000_000, 13, 7, sigma_target=0.03)
+    o = eng.wait(t, n_vox=ph.n_vox)
+    n = o["n_histories"]
+    log(f"  stopped at {n} histories, sigma-bar {o['sigma_bar']:.4f}")
+    assert 1000 <= n < 1_000_000
+    assert o["sigma_bar"] <= 0.03
+    ref = eng.simulate(pid, src, n, 13, 7, n_vox=ph.n_vox, regroup=2)
+    same(o, ref, ph)
+    # an unreachable target runs the maximum
+    t = eng.submit(pid, src, 3000, 13, 8, sigma_target=1e-6)
+    o = eng.wait(t, n_vox=ph.n_vox)
+    assert o["n_histories"] == 3000
+
+
+def test_adaptive_arguments(eng, pool):
+    from paper_0910_0329_amd.mcdose import McdError
+    pid, ph = pool[0]
+    src = sources.pencil(ELECTRON, 20.0, *ph.centre_xy())
+    for tgt, n in ((0.0, 10_000), (1.5, 10_000), (0.01, 10)):
+        with pytest.raises(McdError):
+            eng.submit(pid, src, n, 1, 0, sigma_target=tgt)
