@@ -251,6 +251,34 @@ def main():
             log(f"{wp.name}: {n_p} histories in {tp_:.2f} s (C1060: {t_c1060} s), sigma-bar {rp_['sigma_bar']:.4f}")
     line["paper_geometry"] = paper
 
+    # ------------------------------------------------------------ CT-like phantom
+    wc = configs.photon_6mv_random_field(100_000_000)
+    pc = eng.load_phantom(wc.phantom, th)
+    ct = {"workload": wc.name, "histories": wc.n_histories}
+    doses = {}
+    for fp32 in (0, 1):
+        tc, rc_ = timed(lambda: eng.simulate(pc, wc.source, wc.n_histories, wc.seed, n_vox=wc.phantom.n_vox,
+                                             tally_fp32=fp32), 1)
+        key = "fp32" if fp32 else "fp64"
+        ct[key] = {"hist_per_s": wc.n_histories / tc, "kernel_hist_per_s": wc.n_histories / (rc_["kernel_ms"] * 1e-3),
+                   "sigma_bar": rc_["sigma_bar"], "dmax": rc_["dmax"]}
+        doses[key] = rc_["dose"].cpu().numpy()
+    import numpy as np
+    from paper_0910_0329_amd.inputs.tables import MAT_AIR, MAT_BONE, MAT_LUNG, MAT_WATER
+    mat = wc.phantom.mat.reshape(-1)
+    sel = doses["fp64"] > 0.1 * ct["fp64"]["dmax"]
+    per = {}
+    for name, m in (("air", MAT_AIR), ("lung", MAT_LUNG), ("water", MAT_WATER), ("bone", MAT_BONE)):
+        c = sel & (mat == m)
+        if c.any():
+            rel = np.abs(doses["fp32"][c] - doses["fp64"][c]) / doses["fp64"][c]
+            per[name] = {"voxels": int(c.sum()), "max_rel": float(rel.max()), "median_rel": float(np.median(rel))}
+    ct["fp32_vs_fp64_dose_above_10pct_dmax"] = per
+    del doses
+    eng.unload_phantom(pc)
+    line["ct_phantom"] = ct
+    log(f"ct phantom: fp64 {ct['fp64']['hist_per_s']:.3e} hist/s, fp32 {ct['fp32']['hist_per_s']:.3e}; {per}")
+
     # ------------------------------------------------------------ batched
     from paper_0910_0329_amd import autotune
     srcs, ns = sources.beamlets(wg.phantom, seed=4)
