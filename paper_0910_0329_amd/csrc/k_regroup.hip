@@ -11,8 +11,10 @@
 // Same-type secondaries stay on the lane's own stack, and so does a
 // cross-type secondary when the other queue is full, so no particle is lost
 // and the result does not depend on the queue capacity.  Every lane loops
-// until its phase has no work left; the host (or a captured graph) repeats
-// cycles until all histories are claimed and the queues are empty.
+// until its phase has no work left; the host (or a captured graph) runs
+// cycles until all histories are claimed, and the electron phase of the last
+// cycle keeps the photons it creates on the lane stacks, so nothing is left
+// queued at the end.
 //
 // Histories of several requests (beams, beamlets, served requests) share a
 // launch: each particle carries its request slot, which selects the Philox key

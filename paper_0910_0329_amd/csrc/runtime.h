@@ -23,7 +23,7 @@ constexpr int kDefaultDepth = 64;
 constexpr int kDefaultSlots = 512;
 constexpr int kDefaultChunkPerLane = 16;
 constexpr int kLdsPerCu = 160 * 1024;
-constexpr int kTailCycles = 8;      // cycles scheduled after the last new history
+constexpr int kExtraCycles = 8;     // claim counters kept beyond the planned cycles
 constexpr int kMaxBatch = 4096;
 constexpr int kDefaultFetchDiv = 4;
 constexpr int kDefaultHardDiv = 16;

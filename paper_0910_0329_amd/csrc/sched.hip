@@ -267,14 +267,18 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
     // launch ends with a tail of lanes finishing their last history).
     plan.chunk = plan.use_queues ? std::min<uint64_t>(lanes * (uint64_t)cpl, plan.total)
                                  : std::min<uint64_t>(plan.total, (uint64_t)1 << 31);
-    plan.cycles = (int)((plan.total + plan.chunk - 1) / plan.chunk) + (plan.use_queues ? kTailCycles : 0);
+    // the electron phase of the last cycle keeps its photons on the lane stacks,
+    // so no cycle is needed after the last new history
+    plan.cycles = (int)((plan.total + plan.chunk - 1) / plan.chunk);
 
     // device buffers
     const size_t elem = plan.fp32 ? sizeof(float) : sizeof(double);
     const size_t tally_bytes = extra ? 0 : (size_t)n_req * kBatches * (size_t)ph.nv * elem;
     const size_t stage_bytes = (size_t)n_req * (size_t)ph.nv * sizeof(double);
+    // a full queue is not an error (the particle stays on its lane's stack), so
+    // the capacity is bounded: 2^26 records of 48 B, 3.2 GB per buffer
     const unsigned int cap = plan.use_queues ? (unsigned int)std::min<uint64_t>(
-        std::max<uint64_t>(3 * plan.chunk, 1 << 16), (uint64_t)1 << 30) : (1u << 12);
+        std::max<uint64_t>(2 * plan.chunk, 1 << 16), (uint64_t)1 << 26) : (1u << 12);
     if (keep_tally && (rb.tally_bytes < tally_bytes || rg_owner != phantom || rg_fp32 != plan.fp32 ||
                        n_req != 1))
         return fail(MCD_E_INVAL, "opts.accumulate: no matching regrouped tally to add to");
@@ -288,9 +292,9 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
         have = 0;
         if ((rc = grow((void**)&rb.ctl, &have, 4 * sizeof(QCtl), "queue control"))) return rc;
     }
-    if (rb.claim_cap < plan.cycles + 4 * kTailCycles) {
+    if (rb.claim_cap < plan.cycles + 4 * kExtraCycles) {
         have = (size_t)rb.claim_cap * 4;
-        const int want = plan.cycles + 64 * kTailCycles;
+        const int want = plan.cycles + 64 * kExtraCycles;
         if ((rc = grow((void**)&rb.claim, &have, (size_t)want * 4, "claim counters"))) return rc;
         rb.claim_cap = want;
     }
@@ -377,10 +381,13 @@ int mcd_ctx::enqueue_cycles(const RegroupPlan& plan, int c0, int c1, hipStream_t
         k.q_out = Qe[a];
         k.q_out_ctl = Ce[a];
         k.q_reset_ctl = Cg[b];
+        k.use_queues = plan.use_queues;
         hipError_t e = launch_phase(k, true, plan.blocks, plan.threads, plan.diag, s);
         if (e != hipSuccess) return hip_fail(e, "photon phase launch");
         if (!plan.use_queues) continue;       // nothing is ever queued for it
-        // electron phase: electrons of this photon phase
+        // electron phase: electrons of this photon phase; the last cycle keeps
+        // the photons it creates on the lane stacks
+        k.use_queues = c + 1 < c1 ? 1 : 0;
         k.q_in = Qe[a];
         k.q_in_ctl = Ce[a];
         k.q_out = Qg[b];
@@ -419,8 +426,9 @@ int mcd_ctx::enqueue_regroup(const RegroupPlan& plan, bool clear_tally, hipStrea
     return MCD_OK;
 }
 
-// Waits for the scheduled cycles; if photons are still queued (a longer chain
-// than the scheduled tail), runs more cycles and finalises again.
+// Waits for the scheduled cycles.  The last electron phase keeps its photons
+// on the lane stacks, so no photon should remain queued; if one does, more
+// cycles run and the finalisation is repeated.
 int mcd_ctx::finish_regroup(RegroupPlan& plan, hipStream_t s, int* cycles_run)
 {
     const PhantomRec& ph = phantoms[plan.phantom];
@@ -436,9 +444,9 @@ int mcd_ctx::finish_regroup(RegroupPlan& plan, hipStream_t s, int* cycles_run)
             return fail(err, err == MCD_E_OVERFLOW ? "particle stack overflow: raise stack_depth"
                                                    : "device error in a transport phase");
         if (ctl[done & 1].count == 0) break;      // photons waiting for cycle `done`
-        int rc = enqueue_cycles(plan, done, done + kTailCycles, s);
+        int rc = enqueue_cycles(plan, done, done + 1, s);
         if (rc) return rc;
-        done += kTailCycles;
+        done += 1;
         e = launch_fill_u32(rb.red, (size_t)plan.n_req * 6, 0u, s);
         if (e == hipSuccess) e = hipEventRecord(ev[2], s);
         if (e == hipSuccess)
