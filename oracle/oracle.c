@@ -38,6 +38,9 @@
 
 enum { Q_MUC, Q_MUPE, Q_MUPP, Q_R, Q_L1INV, Q_SM, Q_SB, Q_LR };
 enum { PHOTON = 0, ELECTRON = 1, POSITRON = 2 };
+/* Blob flag: emission angles of photoelectrons (Sauter), bremsstrahlung
+ * photons and pair leptons instead of their parent's direction. */
+#define FLAG_ANGULAR 4u
 
 /* ------------------------------------------------------------------ Philox */
 
@@ -379,6 +382,43 @@ static double sample_brems(stream* s, double t, double w_cr)
     return w_cr * pow(t / w_cr, uni(s));
 }
 
+static double beta_of(double t) { return sqrt(t * (t + 2.0 * MC2)) / (t + MC2); }
+
+/* Forward-peaked emission at leading relativistic order: the polar angle
+ * about the emitter's direction has p(cos) proportional to (1 - beta cos)^-2
+ * on [-1, 1], beta that of an electron of kinetic energy t.  Its CDF inverts
+ * in closed form: cos = (2u - 1 + beta) / (1 - beta + 2 beta u). */
+static double sample_forward_cos(stream* s, double t)
+{
+    double b = beta_of(t);
+    double u = uni(s);
+    return (2.0 * u - 1.0 + b) / (1.0 - b + 2.0 * b * u);
+}
+
+/* Sauter's K-shell photoelectron distribution for an electron of kinetic
+ * energy t, in nu = 1 - cos:
+ *   p(nu) ~ nu (2 - nu) / (A + nu)^4 * (1 + c (A + nu)),
+ *   A = 1/beta - 1,  c = gamma (gamma - 1) (gamma - 2) beta / 2.
+ * With x = nu / (A + nu) the factor nu / (A + nu)^4 dnu becomes x (1 - x) dx
+ * / A^2, so x is drawn from p(x) ~ x on [0, 2 / (A + 2)] and accepted with
+ * probability (1 - x)(2 - nu)(1 + c (A + nu)) / (2 m), m the largest value of
+ * 1 + c (A + nu) on [0, 2] (the factor stays positive for every gamma > 1).
+ * Two uniforms per try. */
+static double sample_sauter_cos(stream* s, double t)
+{
+    double g = 1.0 + t / MC2, b = beta_of(t);
+    double a = 1.0 / b - 1.0;
+    double c = 0.5 * g * (g - 1.0) * (g - 2.0) * b;
+    double xmax = 2.0 / (a + 2.0);
+    double m = c >= 0.0 ? 1.0 + c * (a + 2.0) : 1.0 + c * a;
+    for (;;) {
+        double x = xmax * sqrt(uni(s));
+        double nu = a * x / (1.0 - x);
+        double acc = (1.0 - x) * (2.0 - nu) * (1.0 + c * (a + nu)) / (2.0 * m);
+        if (uni(s) <= acc) return 1.0 - nu;
+    }
+}
+
 /* Random hinge: Wentzel angular law with screening A, mu = (1 - cos)/2 =
  * A u / (1 + A - u). */
 static double sample_hinge_cos(stream* s, double a)
@@ -580,19 +620,36 @@ static void transport_photon(ctx* c, stream* s, double e, double r[3], double d[
             }
             continue;
         }
+        const int angular = (t->flags & FLAG_ANGULAR) != 0;
         if (ev == EV_PHOTO) {
-            /* photon absorbed; the photoelectron takes all of E along d */
+            /* photon absorbed; the photoelectron takes all of E, along d, or
+             * (angular flag, if it is transported) at a Sauter angle to d */
             c->cnt[ORC_C_PHOTO]++;
-            emit(c, s, ELECTRON, e, r, d, v);
+            double de[3] = {d[0], d[1], d[2]};
+            if (angular && e > t->e_abs_e) {
+                double cost = sample_sauter_cos(s, e);
+                rotate(de, cost, 2.0 * PI * uni(s));
+            }
+            emit(c, s, ELECTRON, e, r, de, v);
             return;
         }
-        /* pair: kinetic energy E - 2mc^2 shared uniformly, both along d */
+        /* pair: kinetic energy E - 2mc^2 shared uniformly, both along d, or
+         * (angular flag, each lepton that is transported) at a forward angle */
         c->cnt[ORC_C_PAIR]++;
         double ttot = e - 2.0 * MC2;
         double tm = uni(s) * ttot;
         double tp = ttot - tm;
-        emit(c, s, ELECTRON, tm, r, d, v);
-        emit(c, s, POSITRON, tp, r, d, v);
+        double dm[3] = {d[0], d[1], d[2]}, dp[3] = {d[0], d[1], d[2]};
+        if (angular && tm > t->e_abs_e) {
+            double cost = sample_forward_cos(s, tm);
+            rotate(dm, cost, 2.0 * PI * uni(s));
+        }
+        emit(c, s, ELECTRON, tm, r, dm, v);
+        if (angular && tp > t->e_abs_e) {
+            double cost = sample_forward_cos(s, tp);
+            rotate(dp, cost, 2.0 * PI * uni(s));
+        }
+        emit(c, s, POSITRON, tp, r, dp, v);
         return;
     }
 }
@@ -700,8 +757,12 @@ static void transport_electron(ctx* c, stream* s, int type, double T, double r[3
                 c->cnt[ORC_C_BREMS]++;
                 hash_ev(ph, EV_BREMS);
                 double w = sample_brems(s, T, t->w_cr);
-                (void)uni(s); /* azimuth: drawn for a uniform draw order, unused */
-                emit(c, s, PHOTON, w, r, d, v);
+                /* the photon goes along the electron, or (angular flag) at a
+                 * forward angle to it; the azimuth is drawn either way */
+                double phi = 2.0 * PI * uni(s);
+                double dg[3] = {d[0], d[1], d[2]};
+                if (t->flags & FLAG_ANGULAR) rotate(dg, sample_forward_cos(s, T), phi);
+                emit(c, s, PHOTON, w, r, dg, v);
                 T -= w;
             }
             if (T <= t->e_abs_e) {
@@ -965,7 +1026,7 @@ int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n,
 {
     tables t;
     if (load_tables(blob, nbytes, &t)) return -1;
-    if (which < 0 || which > 3 || !(e > 0.0) || !out) { free(t.q); return -1; }
+    if (which < 0 || which > 5 || !(e > 0.0) || !out) { free(t.q); return -1; }
     if (which == 1 && !(e > 2.0 * t.w_cc)) { free(t.q); return -1; }
     if (which == 2 && !(e > t.w_cr)) { free(t.q); return -1; }
     for (uint64_t i = 0; i < n; ++i) {
@@ -1005,6 +1066,10 @@ int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n,
             o[5] = dd[0]; o[6] = dd[1]; o[7] = dd[2];
         } else if (which == 2) {
             o[0] = sample_brems(&s, e, t.w_cr);
+        } else if (which == 4) {
+            o[0] = sample_sauter_cos(&s, e);
+        } else if (which == 5) {
+            o[0] = sample_forward_cos(&s, e);
         } else {
             double cost = sample_hinge_cos(&s, t.a_hinge);
             double phi = 2.0 * PI * uni(&s);

@@ -110,7 +110,10 @@ int orc_first_interaction(const void* blob, size_t nbytes, const orc_grid* g,
  *   which 1  hard Moller at kinetic energy e: W/T, cos(theta_delta), primary
  *            direction, delta-ray direction
  *   which 2  hard bremsstrahlung at kinetic energy e: W
- *   which 3  random hinge: cos(theta), 0, new direction                       */
+ *   which 3  random hinge: cos(theta), 0, new direction
+ *   which 4  Sauter photoelectron angle at kinetic energy e: cos(theta)
+ *   which 5  forward emission angle (bremsstrahlung photon, pair lepton) for
+ *            an emitter of kinetic energy e: cos(theta)                       */
 int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n, uint32_t seed,
                double* out);
 

@@ -58,6 +58,8 @@ BLOB_MAGIC = b"MCDTAB\x00\x01"
 BLOB_VERSION = 1
 FLAG_NO_HARD = 1                 # test variant: Sigma_M = Sigma_B = 0, unrestricted losses
 FLAG_PE_ONLY = 2                 # test variant: photons interact only by photoabsorption
+FLAG_ANGULAR = 4                 # emission angles of photoelectrons, bremsstrahlung photons
+                                 # and pair leptons (same tables, different samplers)
 
 E_ABS_E = 0.2                   # MeV
 E_ABS_G = 0.05                  # MeV
@@ -246,7 +248,10 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
       "standard"  restricted losses, hard Moller and bremsstrahlung events;
       "no_hard"   no hard events: unrestricted stopping power, Sigma_M = Sigma_B = 0
                   (the CSDA-track-length test case);
-      "pe_only"   standard electrons, photons interact only by photoabsorption.
+      "pe_only"   standard electrons, photons interact only by photoabsorption;
+      "angular"   standard tables; photoelectrons leave at Sauter angles,
+                  bremsstrahlung photons and pair leptons at forward-peaked
+                  angles instead of along their parent.
     """
     e = energy_grid()
     n_mat = len(materials)
@@ -256,6 +261,8 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
         flags |= FLAG_NO_HARD
     elif variant == "pe_only":
         flags |= FLAG_PE_ONLY
+    elif variant == "angular":
+        flags |= FLAG_ANGULAR
     elif variant != "standard":
         raise ValueError(f"unknown table variant {variant!r}")
     w_cc = None if flags & FLAG_NO_HARD else E_ABS_E

@@ -162,6 +162,64 @@ def test_bremsstrahlung_sampler_is_one_over_w(blob, t):
     assert _chi2_pvalue(np.histogram(w, edges)[0], np.full(50, 1 / 50)) > 1e-3
 
 
+@pytest.mark.parametrize("t", [0.25, 1.0, 5.0])
+def test_sauter_photoelectron_angles(t):
+    """Angular flag: the photoelectron polar angle follows Sauter's K-shell
+    distribution (1 - c^2)/(1 - beta c)^4 [1 + gamma(gamma-1)(gamma-2)(1 - beta c)/2],
+    integrated here per bin by quadrature in c = cos(theta)."""
+    blob = T.standard_blob("angular")
+    c = oracle.sample(blob, 4, t, 300_000, seed=24)[:, 0]
+    g = 1 + t / T.MC2
+    beta = math.sqrt(1 - 1 / g ** 2)
+    pdf = lambda x: (1 - x * x) / (1 - beta * x) ** 4 * (1 + 0.5 * g * (g - 1) * (g - 2) * (1 - beta * x))
+    # bins of equal mass in 1/(1 - beta c)^3 resolve the forward peak
+    edges = np.sort(np.concatenate([np.linspace(-1, 1, 41), 1 - np.geomspace(1e-4, 1, 40)]))
+    edges = np.unique(np.clip(edges, -1, 1))
+    pb = np.array([integrate.quad(pdf, a_, b_)[0] for a_, b_ in zip(edges[:-1], edges[1:])])
+    pb /= pb.sum()
+    assert c.min() >= -1 and c.max() <= 1
+    assert _chi2_pvalue(np.histogram(c, edges)[0], pb) > 1e-3
+
+
+@pytest.mark.parametrize("t", [0.3, 2.0, 15.0])
+def test_forward_emission_angles(t):
+    """Angular flag: bremsstrahlung photons and pair leptons leave at a polar
+    angle with density proportional to (1 - beta cos)^-2 about the emitter."""
+    blob = T.standard_blob("angular")
+    c = oracle.sample(blob, 5, t, 300_000, seed=25)[:, 0]
+    g = 1 + t / T.MC2
+    beta = math.sqrt(1 - 1 / g ** 2)
+    pdf = lambda x: 1 / (1 - beta * x) ** 2
+    edges = np.unique(np.concatenate([np.linspace(-1, 1, 41), 1 - np.geomspace(1e-5, 1, 40)]))
+    pb = np.array([integrate.quad(pdf, a_, b_)[0] for a_, b_ in zip(edges[:-1], edges[1:])])
+    pb /= pb.sum()
+    assert _chi2_pvalue(np.histogram(c, edges)[0], pb) > 1e-3
+    # the mean of 1 - cos (which shrinks like 1/gamma) matches its quadrature
+    assert np.mean(1 - c) == pytest.approx(quad_mean(pdf), rel=0.02)
+
+
+def quad_mean(pdf):
+    num = integrate.quad(lambda x: (1 - x) * pdf(x), -1, 1, limit=200, points=[0.999, 0.99999])[0]
+    den = integrate.quad(pdf, -1, 1, limit=200, points=[0.999, 0.99999])[0]
+    return num / den
+
+
+def test_angular_flag_keeps_energy_and_draw_structure(blob):
+    """Same histories with and without the angular flag: energy is conserved,
+    the source sampling is identical, and the angles change the dose."""
+    ph = phantoms.homogeneous(16, 16, 16, 1.0)
+    src = sources.point_field(PHOTON, *ph.centre_xy(), 100.0, 3.0, 3.0, energy=15.0)
+    a = oracle.simulate(blob, ph, src, 3000, seed=81)
+    b = oracle.simulate(T.standard_blob("angular"), ph, src, 3000, seed=81)
+    for r in (a, b):
+        bal = r["bal"]
+        closed = bal["E_csda"] + bal["E_local"] + bal["E_esc"] + bal["E_miss"]
+        assert abs(closed - bal["E_src"]) <= 1e-9 * bal["E_src"]
+    assert a["bal"]["E_src"] == b["bal"]["E_src"]
+    assert a["cnt"]["pair"] > 0 and a["cnt"]["photo"] >= 0
+    assert not np.array_equal(a["S"], b["S"])
+
+
 def test_hinge_reproduces_lewis_first_moment(tabs):
     n = 400_000
     out = oracle.sample(T.standard_blob(), 3, 1.0, n, seed=24)
