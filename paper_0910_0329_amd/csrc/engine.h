@@ -28,6 +28,7 @@ struct DevTables {
     float emin, emax;
     float e_abs_e, e_abs_g, w_cc, w_cr, kappa_step, f_e, a_hinge;
     float f_shift;          // log2(1 - f_e) / (log2 step): (1 - f_e) E is this many nodes below E
+    int angular;            // 1: emission angles for photoelectrons, brems photons, pair leptons
 };
 
 // Source descriptor as the kernels see it.

@@ -238,6 +238,8 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
     ts.kappa_step = rd<double>(s + 48);
     ts.f_e = rd<double>(s + 56);
     ts.a_hinge = rd<double>(s + 64);
+    const uint32_t flags = rd<uint32_t>(s + 72);
+    if (flags & ~7u) return c->fail(MCD_E_INVAL, "table blob: unknown flags");
     if (!(ts.emin > 0 && ts.emax > ts.emin && ts.e_abs_e > ts.emin && ts.e_abs_e < ts.emax &&
           ts.e_abs_g > ts.emin && ts.e_abs_g < ts.emax && ts.w_cc > 0 && ts.w_cr > 0 &&
           ts.kappa_step > 0 && ts.f_e > 0 && ts.f_e < 1 && ts.a_hinge > 0))
@@ -295,6 +297,7 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
     d.w_cr = (float)ts.w_cr;
     d.kappa_step = (float)ts.kappa_step;
     d.f_e = (float)ts.f_e;
+    d.angular = (flags & 4u) ? 1 : 0;
     d.f_shift = (float)(std::log2(1.0 - ts.f_e) * (kNE - 1) / std::log2(ts.emax / ts.emin));
     d.a_hinge = (float)ts.a_hinge;
     ts.live = true;

@@ -327,6 +327,49 @@ struct Transport {
         self().spawn(s);
     }
 
+    // --------------------------------------------------- emission angles
+    // beta of an electron of kinetic energy t, and 1/beta - 1 computed as
+    // 1 / (beta gamma^2 (1 + beta)) (no cancellation near beta = 1)
+    DEV static void beta_a(float t, float& b, float& a)
+    {
+        const float g = 1.f + fdiv(t, kMC2);
+        b = fdiv(sqrtf(t * (t + 2.f * kMC2)), t + kMC2);
+        a = __builtin_amdgcn_rcpf(b * g * g * (1.f + b));
+    }
+
+    // Forward-peaked polar angle about the emitter: p(cos) ~ (1 - beta cos)^-2
+    // on [-1, 1]; inverse CDF cos = (2u - 1 + beta) / (1 - beta + 2 beta u).
+    DEV float forward_cos(Part& q, float t)
+    {
+        float b, a;
+        beta_a(t, b, a);
+        const float omb = a * b;                 // 1 - beta
+        const float u = uni(q);
+        return fminf(fmaxf(fdiv(2.f * u - omb, omb + 2.f * b * u), -1.f), 1.f);
+    }
+
+    // Sauter K-shell photoelectron polar angle.  In nu = 1 - cos the law is
+    // nu (2 - nu) / (A + nu)^4 (1 + c (A + nu)) with A = 1/beta - 1 and
+    // c = gamma (gamma - 1) (gamma - 2) beta / 2; x = nu / (A + nu) is drawn
+    // with density ~ x on [0, 2 / (A + 2)] and accepted with probability
+    // (1 - x)(2 - nu)(1 + c (A + nu)) / (2 m), m the largest value of the last
+    // factor on [0, 2].  Two uniforms per try.
+    DEV float sauter_cos(Part& q, float t)
+    {
+        float b, a;
+        beta_a(t, b, a);
+        const float g = 1.f + fdiv(t, kMC2);
+        const float c = 0.5f * g * (g - 1.f) * (g - 2.f) * b;
+        const float xmax = fdiv(2.f, a + 2.f);
+        const float m = c >= 0.f ? 1.f + c * (a + 2.f) : 1.f + c * a;
+        for (;;) {
+            const float x = xmax * sqrtf(uni(q));
+            const float nu = fdiv(a * x, 1.f - x);
+            const float acc = fdiv((1.f - x) * (2.f - nu) * (1.f + c * (a + nu)), 2.f * m);
+            if (uni(q) <= acc) return fmaxf(1.f - nu, -1.f);
+        }
+    }
+
     // ---------------------------------------------------------- rotation
     // Rotates (u, v, w) by polar cosine cost and azimuth (cos, sin) = (cp, sph).
     DEV static void rotate(float& u, float& v, float& w, float cost, float cp, float sph)
@@ -474,7 +517,15 @@ struct Transport {
         } else if (xs < mu_c + mu_pe) {
             ev(EV_PHOTO);
             count(MCD_C_PHOTO);
-            emit_charged(q, ELECTRON, q.e, q.x, q.y, q.z, q.u, q.v, q.w, vx);
+            // the photoelectron leaves along the photon, or (angular tables,
+            // if it is transported) at a Sauter angle to it
+            float du = q.u, dv = q.v, dw = q.w;
+            if (G().t.angular && q.e > G().t.e_abs_e) {
+                const float cost = sauter_cos(q, q.e);
+                const float ph = uni(q);
+                rotate(du, dv, dw, cost, __builtin_amdgcn_cosf(ph), __builtin_amdgcn_sinf(ph));
+            }
+            emit_charged(q, ELECTRON, q.e, q.x, q.y, q.z, du, dv, dw, vx);
             end_particle(q);
         } else if (xs < mu_c + mu_pe + mu_pp) {
             if (q.e > 2.f * kMC2) {
@@ -483,8 +534,24 @@ struct Transport {
                 const float ttot = q.e - 2.f * kMC2;
                 const float tm = uni(q) * ttot;
                 const float tp = ttot - tm;
-                emit_charged(q, ELECTRON, tm, q.x, q.y, q.z, q.u, q.v, q.w, vx);
-                emit_charged(q, POSITRON, tp, q.x, q.y, q.z, q.u, q.v, q.w, vx);
+                // both leptons along the photon, or (angular tables, each one
+                // that is transported) at a forward angle to it
+                float du = q.u, dv = q.v, dw = q.w;
+                if (G().t.angular && tm > G().t.e_abs_e) {
+                    const float cost = forward_cos(q, tm);
+                    const float ph = uni(q);
+                    rotate(du, dv, dw, cost, __builtin_amdgcn_cosf(ph), __builtin_amdgcn_sinf(ph));
+                }
+                emit_charged(q, ELECTRON, tm, q.x, q.y, q.z, du, dv, dw, vx);
+                du = q.u;
+                dv = q.v;
+                dw = q.w;
+                if (G().t.angular && tp > G().t.e_abs_e) {
+                    const float cost = forward_cos(q, tp);
+                    const float ph = uni(q);
+                    rotate(du, dv, dw, cost, __builtin_amdgcn_cosf(ph), __builtin_amdgcn_sinf(ph));
+                }
+                emit_charged(q, POSITRON, tp, q.x, q.y, q.z, du, dv, dw, vx);
                 end_particle(q);
             } else {
                 ev(EV_PAIR_VOID);
@@ -709,9 +776,16 @@ struct Transport {
             ev(EV_BREMS);
             count(MCD_C_BREMS);
             const float w = fminf(g.t.w_cr * exp2f(uni(q) * __log2f(fdiv(T, g.t.w_cr))), T);
-            (void)uni(q);                          // azimuth, drawn for the draw order
+            // the photon goes along the electron, or (angular tables) at a
+            // forward angle to it; the azimuth is drawn either way
+            const float ph = uni(q);
+            float du = q.u, dv = q.v, dw = q.w;
+            if (g.t.angular) {
+                const float cost = forward_cos(q, T);
+                rotate(du, dv, dw, cost, __builtin_amdgcn_cosf(ph), __builtin_amdgcn_sinf(ph));
+            }
             const float tn = T - w;
-            emit_photon(q, T - tn, q.x, q.y, q.z, q.u, q.v, q.w, vx);
+            emit_photon(q, T - tn, q.x, q.y, q.z, du, dv, dw, vx);
             T = tn;
         }
         q.e = T;

@@ -164,6 +164,32 @@ def test_paper_geometry(eng, blob, th, particle, middle, n, kernel):
     assert f > 0.8
 
 
+@pytest.fixture(scope="module")
+def angular(eng):
+    from paper_0910_0329_amd.inputs import tables
+    blob = tables.standard_blob("angular")
+    return blob, eng.load_materials(blob)
+
+
+@pytest.mark.parametrize("kernel", ("plain", "regrouped"))
+@pytest.mark.parametrize("particle,e,n", [(PHOTON, 18.0, 6_000), (ELECTRON, 15.0, 3_000), (PHOTON, 0.6, 40_000)])
+def test_angular_tables_match_oracle(eng, angular, particle, e, n, kernel):
+    """Tables with the angular flag: photoelectrons at Sauter angles,
+    bremsstrahlung photons and pair leptons at forward-peaked angles."""
+    blob, tha = angular
+    ph = phantoms.random_field_phantom(40, 0.25, seed=54, nz=48)
+    x, y = ph.centre_xy()
+    src = sources.point_field(particle, x, y, 60.0, 3.0, 2.0, energy=e)
+    log(f"case angular particle={particle} e={e} n={n} kernel={kernel}")
+    g, ref = run_both(eng, blob, tha, ph, src, n, seed=17, key=5, kernel=kernel)
+    check_dose(ph, g, ref, n, kernel)
+    check_balance(g, ref)
+    f = match_fraction(g, ref)
+    log(f"  history match fraction {f:.4f}")
+    assert f > 0.8
+    assert g["cnt"]["photo"] + g["cnt"]["pair"] + g["cnt"]["brems"] > 0
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_split_runs_and_repeatability(eng, th, kernel):
     w = configs.electron_20mev_wlw(4000)
