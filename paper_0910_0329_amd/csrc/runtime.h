@@ -119,6 +119,8 @@ namespace mcd {
 // Uploads the request tables of a plan and runs it on stream s (captured in a
 // graph and replayed when use_graph); returns when the device is done.
 int run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_graph, hipStream_t s);
+// Records per particle queue for cycles of `chunk` new histories.
+unsigned int queue_capacity(uint64_t chunk);
 }  // namespace mcd
 
 struct mcd_ctx {

@@ -201,6 +201,14 @@ int mcd_ctx::simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n_h
 
 // --------------------------------------------------------- regrouped engine
 
+// Records per particle queue for cycles of `chunk` new histories.  A full
+// queue is not an error (the particle stays on its lane's stack), so the
+// capacity is bounded: 2^26 records of 48 B, 3.2 GB per buffer.
+unsigned int mcd::queue_capacity(uint64_t chunk)
+{
+    return (unsigned int)std::min<uint64_t>(std::max<uint64_t>(2 * chunk, 1 << 16), (uint64_t)1 << 26);
+}
+
 // Histories h in [first, first + n) with h mod kBatches == b.
 static double batch_count(uint64_t first, uint64_t n, int b)
 {
@@ -275,10 +283,7 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
     const size_t elem = plan.fp32 ? sizeof(float) : sizeof(double);
     const size_t tally_bytes = extra ? 0 : (size_t)n_req * kBatches * (size_t)ph.nv * elem;
     const size_t stage_bytes = (size_t)n_req * (size_t)ph.nv * sizeof(double);
-    // a full queue is not an error (the particle stays on its lane's stack), so
-    // the capacity is bounded: 2^26 records of 48 B, 3.2 GB per buffer
-    const unsigned int cap = plan.use_queues ? (unsigned int)std::min<uint64_t>(
-        std::max<uint64_t>(2 * plan.chunk, 1 << 16), (uint64_t)1 << 26) : (1u << 12);
+    const unsigned int cap = plan.use_queues ? queue_capacity(plan.chunk) : (1u << 12);
     if (keep_tally && (rb.tally_bytes < tally_bytes || rg_owner != phantom || rg_fp32 != plan.fp32 ||
                        n_req != 1))
         return fail(MCD_E_INVAL, "opts.accumulate: no matching regrouped tally to add to");

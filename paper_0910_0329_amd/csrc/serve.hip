@@ -78,6 +78,7 @@ struct mcd_server {
     std::vector<Request*> active;                        // ADMITTED or RUNNING
     int last_phantom = -1;
     uint64_t req_bytes = 0;                              // memory held by requests
+    bool mem_blocked = false;                            // the queue head waits for memory to be freed
     mcd_serve_stats stats{};
 };
 
@@ -85,10 +86,10 @@ struct mcd_server {
 
 static void free_request_memory(mcd_ctx* c, Request* r, bool outputs_too)
 {
+    mcd_server* S = c->server;
     {
-        std::lock_guard<std::mutex> g(c->server->mu);
-        c->server->req_bytes -= std::min<uint64_t>(c->server->req_bytes,
-                                                   r->tally_bytes + (outputs_too ? 2 * r->out_bytes : 0));
+        std::lock_guard<std::mutex> g(S->mu);
+        S->req_bytes -= std::min<uint64_t>(S->req_bytes, r->tally_bytes + (outputs_too ? 2 * r->out_bytes : 0));
     }
     c->release(r->tally, r->tally_bytes);
     r->tally = nullptr;
@@ -99,6 +100,10 @@ static void free_request_memory(mcd_ctx* c, Request* r, bool outputs_too)
         r->dose = r->sigma = nullptr;
         r->out_bytes = 0;
     }
+    // a queued request may fit now
+    std::lock_guard<std::mutex> g(S->mu);
+    S->mem_blocked = false;
+    S->cv_work.notify_one();
 }
 
 // Ends a request (under the server mutex).
@@ -145,24 +150,24 @@ static void admit(mcd_ctx* c, mcd_server* S)
             if (lanes_b > c->rb.scratch_bytes) reserve += lanes_b - c->rb.scratch_bytes;
             if (S->cfg.opts.regroup == 1) {
                 const int cpl = S->cfg.opts.chunk_per_lane ? S->cfg.opts.chunk_per_lane : kDefaultChunkPerLane;
-                const uint64_t cap = std::min<uint64_t>(std::max<uint64_t>(3 * lanes * cpl, 1 << 16),
-                                                        (uint64_t)1 << 30);
+                const unsigned int cap = queue_capacity(lanes * (uint64_t)cpl);
                 if (cap > c->rb.cap) reserve += (size_t)4 * (cap - c->rb.cap) * kRec;
             }
         }
-        bool fits;
+        // fits now, or only once other requests free their memory (the ones
+        // running, and finished ones whose results are not collected yet)
+        bool fits, never;
         {
             std::lock_guard<std::mutex> g(c->mu_alloc);
-            fits = c->used + tb + 2 * ob + reserve <= c->budget;
-        }
-        const bool never = S->cfg.memory_limit && tb + 2 * ob > S->cfg.memory_limit;
-        {
-            std::lock_guard<std::mutex> g(S->mu);
-            if (S->cfg.memory_limit && S->req_bytes + tb + 2 * ob > S->cfg.memory_limit) fits = false;
+            std::lock_guard<std::mutex> g2(S->mu);
+            const uint64_t need = tb + 2 * ob;
+            const uint64_t others = c->used - std::min<uint64_t>(c->used, S->req_bytes);
+            fits = c->used + need + reserve <= c->budget &&
+                   (!S->cfg.memory_limit || S->req_bytes + need <= S->cfg.memory_limit);
+            never = others + need + reserve > c->budget || (S->cfg.memory_limit && need > S->cfg.memory_limit);
         }
         int rc = MCD_E_NOMEM;
-        std::string why = never ? "request needs more device memory than the serving memory limit"
-                                : "request needs more device memory than the HBM budget";
+        std::string why = "request needs more device memory than the HBM budget or the serving memory limit";
         if (fits) {
             rc = c->alloc(&r->tally, tb, "request tally");
             if (rc == MCD_OK) r->tally_bytes = tb;
@@ -195,7 +200,12 @@ static void admit(mcd_ctx* c, mcd_server* S)
                 S->active.push_back(r);
                 continue;
             }
-            if (!cancelled && !never && !S->active.empty()) return;   // wait for memory to be freed
+            if (!cancelled && !never && rc == MCD_E_NOMEM && !fits) {
+                // wait for memory: epochs of the active requests free theirs,
+                // collecting finished requests frees theirs
+                if (S->active.empty()) S->mem_blocked = true;
+                return;
+            }
             S->pending.pop_front();
             if (!cancelled) {                                // can never fit
                 end_request(S, r, MCD_FAILED, MCD_E_NOMEM, why);
@@ -380,7 +390,9 @@ static void serve_loop(mcd_ctx* c)
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_work.wait(lk, [S] { return S->stop || !S->pending.empty() || !S->active.empty(); });
+            S->cv_work.wait(lk, [S] {
+                return S->stop || !S->active.empty() || (!S->pending.empty() && !S->mem_blocked);
+            });
             if (S->stop) return;
         }
         std::lock_guard<std::mutex> run(c->run_mu);
@@ -525,6 +537,8 @@ int mcd_cancel(mcd_ctx* c, uint64_t ticket)
     if (r->state == MCD_QUEUED && !r->admitting) {
         S->pending.erase(std::find(S->pending.begin(), S->pending.end(), r));
         end_request(S, r, MCD_CANCELED, MCD_E_CANCELED, "request cancelled");
+        S->mem_blocked = false;              // the next request may fit
+        S->cv_work.notify_one();
     } else if (r->state == MCD_QUEUED || r->state == MCD_ADMITTED || r->state == MCD_RUNNING) {
         r->cancel = true;
         S->cv_work.notify_one();

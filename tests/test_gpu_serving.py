@@ -247,3 +247,26 @@ def test_adaptive_arguments(eng, pool):
     for tgt, n in ((0.0, 10_000), (1.5, 10_000), (0.01, 10)):
         with pytest.raises(McdError):
             eng.submit(pid, src, n, 1, 0, sigma_target=tgt)
+
+
+def test_admission_waits_for_results_to_be_collected(eng, pool):
+    """A request that fits only once an earlier finished request's results are
+    collected waits for that (it is not failed), then completes."""
+    from paper_0910_0329_amd.mcdose import QUEUED
+    pid, ph = pool[0]
+    src = sources.pencil(ELECTRON, 20.0, *ph.centre_xy())
+    one = 18 * ph.n_vox * 8
+    eng.serve_configure(epoch_histories=5000, memory_limit=int(1.05 * one), regroup=2)
+    log("case serve admission waits for collection")
+    a = eng.submit(pid, src, 2000, 3, 1)
+    b = eng.submit(pid, src, 2000, 3, 2)
+    for _ in range(400):                      # a finishes; its dose and sigma stay held
+        if eng.poll(a)[0] != QUEUED and eng.poll(a)[0] >= 3:
+            break
+        time.sleep(0.005)
+    time.sleep(0.05)
+    assert eng.poll(b)[0] == QUEUED
+    ra = eng.wait(a, n_vox=ph.n_vox)          # frees a's results: b is admitted
+    rb = eng.wait(b, n_vox=ph.n_vox, timeout_ms=60_000)
+    same(ra, eng.simulate(pid, src, 2000, 3, 1, n_vox=ph.n_vox, regroup=2), ph)
+    same(rb, eng.simulate(pid, src, 2000, 3, 2, n_vox=ph.n_vox, regroup=2), ph)
