@@ -239,7 +239,7 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
     ts.f_e = rd<double>(s + 56);
     ts.a_hinge = rd<double>(s + 64);
     const uint32_t flags = rd<uint32_t>(s + 72);
-    if (flags & ~7u) return c->fail(MCD_E_INVAL, "table blob: unknown flags");
+    if (flags & ~15u) return c->fail(MCD_E_INVAL, "table blob: unknown flags");
     if (!(ts.emin > 0 && ts.emax > ts.emin && ts.e_abs_e > ts.emin && ts.e_abs_e < ts.emax &&
           ts.e_abs_g > ts.emin && ts.e_abs_g < ts.emax && ts.w_cc > 0 && ts.w_cr > 0 &&
           ts.kappa_step > 0 && ts.f_e > 0 && ts.f_e < 1 && ts.a_hinge > 0))

@@ -550,6 +550,7 @@ int mcd::run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_g
         add(&plan.depth, sizeof plan.depth);
         add(&plan.fp32, sizeof plan.fp32);
         add(&plan.diag, sizeof plan.diag);
+        add(&plan.use_queues, sizeof plan.use_queues);
         add(&plan.sched, sizeof plan.sched);
         add(&clear_tally, sizeof clear_tally);
         add(&c->rb, sizeof c->rb);

@@ -60,6 +60,8 @@ FLAG_NO_HARD = 1                 # test variant: Sigma_M = Sigma_B = 0, unrestri
 FLAG_PE_ONLY = 2                 # test variant: photons interact only by photoabsorption
 FLAG_ANGULAR = 4                 # emission angles of photoelectrons, bremsstrahlung photons
                                  # and pair leptons (same tables, different samplers)
+FLAG_DENSITY = 8                 # collision stopping power with the density effect
+                                 # (tables only: range and total stopping power change)
 
 E_ABS_E = 0.2                   # MeV
 E_ABS_G = 0.05                  # MeV
@@ -140,9 +142,56 @@ def _kin(t: float):
     return tau, pc, beta2
 
 
-def l_col(m: Material, t: float, w_cut: float | None) -> float:
+LN10 = math.log(10.0)
+GAS_DENSITY = 0.01               # g/cm^3: below it a material takes the gas rules
+
+
+def density_effect_params(m: Material):
+    """Sternheimer-Peierls general parameters of the density-effect correction
+    for a material at its nominal density (no conduction electrons):
+      plasma energy  h w_p = 28.816 sqrt(rho Z/A) eV,
+      C = 2 ln(I / h w_p) + 1,
+      (X0, X1) from C by the rules for condensed materials (I below or above
+      100 eV) or for gases, exponent k = 3, and a = (C - 2 ln10 X0) / (X1 - X0)^k
+      so that the correction starts continuously at X0.
+    Returns (C, X0, X1, a, k)."""
+    hwp = 28.816 * math.sqrt(m.rho * m.zoa)
+    c = 2.0 * math.log(m.i_ev / hwp) + 1.0
+    if m.rho < GAS_DENSITY:
+        rules = ((10.0, 1.6, 4.0), (10.5, 1.7, 4.0), (11.0, 1.8, 4.0), (11.5, 1.9, 4.0),
+                 (12.25, 2.0, 4.0), (13.804, 2.0, 5.0))
+        x0, x1 = 0.326 * c - 2.5, 5.0
+        for c_top, x0_r, x1_r in rules:
+            if c < c_top:
+                x0, x1 = x0_r, x1_r
+                break
+    elif m.i_ev < 100.0:
+        x1 = 2.0
+        x0 = 0.2 if c < 3.681 else 0.326 * c - 1.0
+    else:
+        x1 = 3.0
+        x0 = 0.2 if c < 5.215 else 0.326 * c - 1.5
+    k = 3.0
+    a = (c - 2.0 * LN10 * x0) / (x1 - x0) ** k
+    return c, x0, x1, a, k
+
+
+def density_delta(m: Material, t: float) -> float:
+    """Density-effect correction delta at kinetic energy t, as a function of
+    X = log10(p / (m c)):  0 below X0,  2 ln10 X - C + a (X1 - X)^k up to X1,
+    2 ln10 X - C above."""
+    c, x0, x1, a, k = density_effect_params(m)
+    x = math.log10(math.sqrt(t * (t + 2.0 * MC2)) / MC2)
+    if x < x0:
+        return 0.0
+    d = 2.0 * LN10 * x - c
+    return d + a * (x1 - x) ** k if x < x1 else d
+
+
+def l_col(m: Material, t: float, w_cut: float | None, density: bool = False) -> float:
     """Bethe collision stopping power with Moller F-, restricted to energy losses
-    below w_cut (None: unrestricted).  No density effect."""
+    below w_cut (None: unrestricted); with `density`, less the density-effect
+    correction delta of the material at its nominal density."""
     tau, _, beta2 = _kin(t)
     dmax = t / 2.0
     w = dmax if w_cut is None else min(w_cut, dmax)
@@ -151,7 +200,8 @@ def l_col(m: Material, t: float, w_cut: float | None) -> float:
     f = (-1.0 - beta2 + math.log((tau - d) * d) + tau / (tau - d)
          + (d * d / 2.0 + (2.0 * tau + 1.0) * math.log1p(-d / tau)) / (tau + 1.0) ** 2)
     pref = 2.0 * math.pi * R_E ** 2 * MC2 * N_A * m.zoa / beta2
-    return pref * (math.log(2.0 * (tau + 2.0) / i_mc2 ** 2) + f)
+    delta = density_delta(m, t) if density else 0.0
+    return pref * (math.log(2.0 * (tau + 2.0) / i_mc2 ** 2) + f - delta)
 
 
 def l_rad(m: Material, t: float, w_cut: float | None) -> float:
@@ -251,7 +301,9 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
       "pe_only"   standard electrons, photons interact only by photoabsorption;
       "angular"   standard tables; photoelectrons leave at Sauter angles,
                   bremsstrahlung photons and pair leptons at forward-peaked
-                  angles instead of along their parent.
+                  angles instead of along their parent;
+      "density"   standard, with the density effect in the collision stopping
+                  power (and so in the range).
     """
     e = energy_grid()
     n_mat = len(materials)
@@ -263,13 +315,17 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
         flags |= FLAG_PE_ONLY
     elif variant == "angular":
         flags |= FLAG_ANGULAR
+    elif variant == "density":
+        flags |= FLAG_DENSITY
     elif variant != "standard":
         raise ValueError(f"unknown table variant {variant!r}")
     w_cc = None if flags & FLAG_NO_HARD else E_ABS_E
     w_cr = None if flags & FLAG_NO_HARD else E_ABS_G
     for mi, m in enumerate(materials):
-        def lr(t, m=m):
-            return l_col(m, t, w_cc) + l_rad(m, t, w_cr)
+        dens = bool(flags & FLAG_DENSITY)
+
+        def lr(t, m=m, dens=dens):
+            return l_col(m, t, w_cc, dens) + l_rad(m, t, w_cr)
         for i, ei in enumerate(e):
             if not flags & FLAG_PE_ONLY:
                 data[mi, Q_MU_C, i] = mu_compton(m, ei)

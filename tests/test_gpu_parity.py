@@ -190,6 +190,24 @@ def test_angular_tables_match_oracle(eng, angular, particle, e, n, kernel):
     assert g["cnt"]["photo"] + g["cnt"]["pair"] + g["cnt"]["brems"] > 0
 
 
+@pytest.mark.parametrize("kernel", ("plain", "regrouped"))
+def test_density_effect_tables_match_oracle(eng, kernel):
+    """Tables with the density effect in the collision stopping power: the
+    same transport code on different ranges and stopping powers."""
+    from paper_0910_0329_amd.inputs import tables
+    blob = tables.standard_blob("density")
+    thd = eng.load_materials(blob)
+    w = configs.electron_20mev_wlw(8_000)
+    log(f"case density-effect tables e20_wlw kernel={kernel}")
+    g, ref = run_both(eng, blob, thd, w.phantom, w.source, w.n_histories, w.seed, kernel=kernel)
+    check_dose(w.phantom, g, ref, w.n_histories, kernel)
+    check_balance(g, ref)
+    f = match_fraction(g, ref)
+    log(f"  history match fraction {f:.4f}")
+    assert f > 0.8
+    eng.unload_materials(thd)
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_split_runs_and_repeatability(eng, th, kernel):
     w = configs.electron_20mev_wlw(4000)

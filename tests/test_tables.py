@@ -223,3 +223,38 @@ def test_spectrum_mean():
     assert len(w) == 64
     s = sources.Source(energy_kind=sources.HISTOGRAM, edges=edges, weights=w)
     assert s.mean_energy() == pytest.approx(2.067, abs=2e-3)
+
+
+def test_density_effect_is_continuous():
+    """delta starts at zero at X0 (the definition of a) and joins its
+    asymptote smoothly at X1 (the (X1 - X)^3 term and its slope vanish)."""
+    for m in T.MATERIALS:
+        c, x0, x1, a, k = T.density_effect_params(m)
+        t_at = lambda x: T.MC2 * (math.sqrt(1.0 + 10.0 ** (2 * x)) - 1.0)    # X -> kinetic energy
+        assert T.density_delta(m, t_at(x0 - 1e-9)) == 0.0
+        assert T.density_delta(m, t_at(x0 + 1e-9)) == pytest.approx(0.0, abs=1e-7)
+        lo, hi = T.density_delta(m, t_at(x1 - 1e-7)), T.density_delta(m, t_at(x1 + 1e-7))
+        assert lo == pytest.approx(hi, abs=1e-5)
+        assert hi == pytest.approx(2 * math.log(10) * x1 - c, abs=1e-5)
+
+
+def test_density_effect_plateau_does_not_depend_on_i():
+    """Above X1, delta = 2 ln(p/mc) - 2 ln(I / h w_p) - 1 cancels the ln I of
+    the Bethe formula: two media that differ only in I lose the same energy."""
+    a = T.Material("a", 1.0, 0.5551, 60.0, 3.664, 4.219, 227.5)
+    b = T.Material("b", 1.0, 0.5551, 90.0, 3.664, 4.219, 227.5)
+    for t in (100.0, 300.0):
+        assert T.l_col(a, t, 0.2, True) == pytest.approx(T.l_col(b, t, 0.2, True), rel=1e-12)
+        assert T.l_col(a, t, 0.2) != pytest.approx(T.l_col(b, t, 0.2), rel=1e-3)
+
+
+def test_density_effect_only_lowers_high_energy_losses():
+    w = T.MATERIALS[T.MAT_WATER]
+    assert T.l_col(w, 0.2, 0.2, True) == T.l_col(w, 0.2, 0.2)          # below X0
+    for t in (1.0, 5.0, 20.0):
+        assert T.l_col(w, t, 0.2, True) < T.l_col(w, t, 0.2)
+    std, den = T.build_tables(variant="standard"), T.build_tables(variant="density")
+    assert den.flags == T.FLAG_DENSITY
+    r_std, r_den = std.data[T.MAT_WATER, T.Q_RANGE], den.data[T.MAT_WATER, T.Q_RANGE]
+    assert r_den[-1] > r_std[-1]
+    np.testing.assert_array_equal(std.data[:, T.Q_MU_C], den.data[:, T.Q_MU_C])
