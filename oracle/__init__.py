@@ -21,7 +21,7 @@ BAL_NAMES = ("E_src", "E_csda", "E_local", "E_esc", "E_miss", "track_e")
 COUNT_NAMES = ("histories", "flights", "virtual", "compton", "photo", "pair", "segments",
                "seg_E", "seg_h", "seg_k", "seg_b", "seg_f", "hinges", "moller", "brems",
                "spawns", "philox", "flushes", "escapes", "misses", "local", "void",
-               "compton_tries", "moller_tries", "max_stack")
+               "compton_tries", "moller_tries", "max_stack", "rayleigh")
 
 
 class Grid(C.Structure):
@@ -204,6 +204,7 @@ def simulate_parallel(blob, ph, src, n, seed, key=0, first=0, procs=None) -> dic
             bal += b_
             cnt[:24] += c_[:24]
             cnt[24] = max(cnt[24], c_[24])
+            cnt[25:] += c_[25:]
     return {"S": S, "Q": Q, "bal": dict(zip(BAL_NAMES, bal)), "bal_raw": bal,
             "cnt": dict(zip(COUNT_NAMES, (int(x) for x in cnt))), "cnt_raw": cnt, "n": n,
             "procs": len(jobs)}

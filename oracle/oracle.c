@@ -34,9 +34,11 @@
 #define MC2 0.51099895              /* MeV */
 #define MEV_PER_G_TO_GY 1.602176634e-10
 #define NE 512
-#define NQ 8
+#define NQ 9
+#define A0 5.29177210903e-9         /* Bohr radius, cm */
+#define HBARC 1.973269804e-11       /* MeV cm */
 
-enum { Q_MUC, Q_MUPE, Q_MUPP, Q_R, Q_L1INV, Q_SM, Q_SB, Q_LR };
+enum { Q_MUC, Q_MUPE, Q_MUPP, Q_R, Q_L1INV, Q_SM, Q_SB, Q_LR, Q_MUR };
 enum { PHOTON = 0, ELECTRON = 1, POSITRON = 2 };
 /* Blob flag: emission angles of photoelectrons (Sauter), bremsstrahlung
  * photons and pair leptons instead of their parent's direction. */
@@ -76,6 +78,7 @@ typedef struct {
     double emin, emax, e_abs_e, e_abs_g, w_cc, w_cr, kappa_step, f_e, a_hinge;
     uint32_t flags;
     double ln_emin, dlog;          /* ln E_0 and the grid step in ln E */
+    double ray_b[256];             /* Rayleigh form factor: b = ray_b[m] E^2 */
     double* q;                     /* [n_mat][NQ][NE] */
 } tables;
 
@@ -90,7 +93,7 @@ static int load_tables(const void* blob, size_t nbytes, tables* t)
 {
     const unsigned char* b = (const unsigned char*)blob;
     if (!blob || nbytes < HDR_BYTES || memcmp(b, "MCDTAB\0\1", 8) != 0) return -1;
-    if (rd_u32(b + 8) != 1 || rd_u32(b + 16) != NE || rd_u32(b + 20) != NQ) return -1;
+    if (rd_u32(b + 8) != 2 || rd_u32(b + 16) != NE || rd_u32(b + 20) != NQ) return -1;
     int n_mat = (int)rd_u32(b + 12);
     if (n_mat < 1 || n_mat > 255 || nbytes != (size_t)HDR_BYTES + (size_t)n_mat * MAT_BYTES)
         return -1;
@@ -109,8 +112,13 @@ static int load_tables(const void* blob, size_t nbytes, tables* t)
     t->q = (double*)malloc(sizeof(double) * (size_t)n_mat * NQ * NE);
     if (!t->q) return -1;
     for (int m = 0; m < n_mat; ++m) {
-        const unsigned char* mp = b + HDR_BYTES + (size_t)m * MAT_BYTES + 16 + 6 * 8;
-        memcpy(t->q + (size_t)m * NQ * NE, mp, sizeof(double) * NQ * NE);
+        const unsigned char* mh = b + HDR_BYTES + (size_t)m * MAT_BYTES + 16;
+        memcpy(t->q + (size_t)m * NQ * NE, mh + 6 * 8, sizeof(double) * NQ * NE);
+        /* screening radius a = 0.885 a0 Z_s^(-1/3), Z_s = B / (Z/A) from the
+         * material header (rho, Z/A, I, B, ...); b = 2 (k a)^2, k = E / (hbar c) */
+        double zoa = rd_f64(mh + 8), bz = rd_f64(mh + 24);
+        double a = 0.885 * A0 * pow(bz / zoa, -1.0 / 3.0);
+        t->ray_b[m] = 2.0 * a * a / (HBARC * HBARC);
     }
     for (size_t i = 0; i < (size_t)n_mat * NQ * NE; ++i)
         if (!(t->q[i] >= 0.0) || !isfinite(t->q[i])) { free(t->q); return -1; }
@@ -243,7 +251,8 @@ static void build_majorant(const tables* t, const geom* G, double* mu)
         double best = 0.0;
         for (int m = 0; m < t->n_mat; ++m) {
             if (rmax[m] <= 0.0) continue;
-            double s = tab(t, m, Q_MUC)[i] + tab(t, m, Q_MUPE)[i] + tab(t, m, Q_MUPP)[i];
+            double s = tab(t, m, Q_MUC)[i] + tab(t, m, Q_MUPE)[i] + tab(t, m, Q_MUPP)[i] +
+                       tab(t, m, Q_MUR)[i];
             if (rmax[m] * s > best) best = rmax[m] * s;
         }
         mu[i] = best;
@@ -419,6 +428,23 @@ static double sample_sauter_cos(stream* s, double t)
     }
 }
 
+/* Rayleigh polar angle: p(c) ~ (1 + c^2) (1 + b (1 - c))^-4 (screened
+ * Thomson law), b = ray_b[m] E^2.  s = 1 - c is drawn from (1 + b s)^-4 on
+ * [0, 2] by inverting its CDF,
+ *   (1 + b s)^-3 = 1 - u (1 - (1 + 2b)^-3),
+ * written with log1p / expm1, and accepted with probability (1 + c^2) / 2.
+ * Two uniforms per try. */
+static double sample_rayleigh_cos(stream* s, double b)
+{
+    double w = -expm1(-3.0 * log1p(2.0 * b));
+    for (;;) {
+        double u = uni(s);
+        double sd = b > 0.0 ? expm1(-log1p(-u * w) / 3.0) / b : 2.0 * u;
+        double c = 1.0 - sd;
+        if (uni(s) <= 0.5 * (1.0 + c * c)) return c;
+    }
+}
+
 /* Random hinge: Wentzel angular law with screening A, mu = (1 - cos)/2 =
  * A u / (1 + A - u). */
 static double sample_hinge_cos(stream* s, double a)
@@ -461,7 +487,7 @@ typedef struct {
 static uint64_t hash_init(uint64_t lineage) { return (0xcbf29ce484222325ull ^ lineage) * 0x100000001b3ull; }
 static void hash_ev(uint64_t* hp, uint32_t code) { *hp = (*hp ^ code) * 0x100000001b3ull; }
 
-enum { EV_VIRTUAL = 1, EV_COMPTON, EV_PHOTO, EV_PAIR, EV_PAIR_VOID, EV_G_ESCAPE, EV_G_ABSORB,
+enum { EV_VIRTUAL = 1, EV_COMPTON, EV_PHOTO, EV_PAIR, EV_PAIR_VOID, EV_G_ESCAPE, EV_G_ABSORB, EV_RAYLEIGH,
        EV_SEG = 10, EV_MOLLER = 20, EV_BREMS, EV_MOLLER_VOID, EV_E_ESCAPE };
 
 static void deposit(ctx* c, size_t v, double e, int channel)
@@ -570,10 +596,12 @@ static int photon_flight(ctx* c, stream* s, double e, double r[3], const double 
     double mu_c = rho * interp(t, tab(t, m, Q_MUC), e);
     double mu_pe = rho * interp(t, tab(t, m, Q_MUPE), e);
     double mu_pp = rho * interp(t, tab(t, m, Q_MUPP), e);
+    double mu_r = rho * interp(t, tab(t, m, Q_MUR), e);
     double x = uni(s) * mu_max;
     if (x < mu_c) return EV_COMPTON;
     if (x < mu_c + mu_pe) return EV_PHOTO;
     if (x < mu_c + mu_pe + mu_pp) return e > 2.0 * MC2 ? EV_PAIR : EV_PAIR_VOID;
+    if (x < mu_c + mu_pe + mu_pp + mu_r) return EV_RAYLEIGH;
     return EV_VIRTUAL;
 }
 
@@ -593,6 +621,14 @@ static void transport_photon(ctx* c, stream* s, double e, double r[3], double d[
         size_t v = lin_voxel(c->G, idx);
         if (ev == EV_VIRTUAL || ev == EV_PAIR_VOID) {
             c->cnt[ev == EV_VIRTUAL ? ORC_C_VIRTUAL : ORC_C_VOID]++;
+            continue;
+        }
+        if (ev == EV_RAYLEIGH) {
+            /* coherent: the photon keeps its energy and turns by a screened
+             * Thomson angle */
+            c->cnt[ORC_C_RAYLEIGH]++;
+            double cost = sample_rayleigh_cos(s, t->ray_b[c->G->mat[v]] * e * e);
+            rotate(d, cost, 2.0 * PI * uni(s));
             continue;
         }
         if (ev == EV_COMPTON) {
@@ -1026,7 +1062,7 @@ int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n,
 {
     tables t;
     if (load_tables(blob, nbytes, &t)) return -1;
-    if (which < 0 || which > 5 || !(e > 0.0) || !out) { free(t.q); return -1; }
+    if (which < 0 || which >= 6 + t.n_mat || !(e > 0.0) || !out) { free(t.q); return -1; }
     if (which == 1 && !(e > 2.0 * t.w_cc)) { free(t.q); return -1; }
     if (which == 2 && !(e > t.w_cr)) { free(t.q); return -1; }
     for (uint64_t i = 0; i < n; ++i) {
@@ -1070,6 +1106,8 @@ int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n,
             o[0] = sample_sauter_cos(&s, e);
         } else if (which == 5) {
             o[0] = sample_forward_cos(&s, e);
+        } else if (which >= 6) {
+            o[0] = sample_rayleigh_cos(&s, t.ray_b[which - 6] * e * e);
         } else {
             double cost = sample_hinge_cos(&s, t.a_hinge);
             double phi = 2.0 * PI * uni(&s);

@@ -19,6 +19,8 @@ Quantities per material, per gram (the order is the blob's quantity index):
   5  Sigma_M/rho  hard Moller cross section (W > W_cc)         cm^2/g
   6  Sigma_B/rho  hard bremsstrahlung cross section (W > W_cr) cm^2/g
   7  L_r/rho      restricted total stopping power              MeV cm^2/g
+  8  mu_R/rho     Rayleigh (coherent) scattering, screened     cm^2/g
+                  Thomson law (zero unless the tables enable it)
 
 Absorption energies are 200 keV (electrons) and 50 keV (photons) (Sec. 3);
 the production thresholds W_cc and W_cr are taken equal to them.
@@ -49,19 +51,20 @@ K_B = 5.07e-3                   # cm^2 / g, bremsstrahlung
 N_E = 512
 E_MIN = 1.0e-3                  # MeV
 E_MAX = 20.0                    # MeV
-N_Q = 8
+N_Q = 9
 
-Q_MU_C, Q_MU_PE, Q_MU_PP, Q_RANGE, Q_LAMBDA1_INV, Q_SIGMA_M, Q_SIGMA_B, Q_L_R = range(8)
-QUANTITY_NAMES = ("mu_C", "mu_pe", "mu_pp", "R", "lambda1_inv", "Sigma_M", "Sigma_B", "L_r")
+Q_MU_C, Q_MU_PE, Q_MU_PP, Q_RANGE, Q_LAMBDA1_INV, Q_SIGMA_M, Q_SIGMA_B, Q_L_R, Q_MU_R = range(9)
+QUANTITY_NAMES = ("mu_C", "mu_pe", "mu_pp", "R", "lambda1_inv", "Sigma_M", "Sigma_B", "L_r", "mu_R")
 
 BLOB_MAGIC = b"MCDTAB\x00\x01"
-BLOB_VERSION = 1
+BLOB_VERSION = 2
 FLAG_NO_HARD = 1                 # test variant: Sigma_M = Sigma_B = 0, unrestricted losses
 FLAG_PE_ONLY = 2                 # test variant: photons interact only by photoabsorption
 FLAG_ANGULAR = 4                 # emission angles of photoelectrons, bremsstrahlung photons
                                  # and pair leptons (same tables, different samplers)
 FLAG_DENSITY = 8                 # collision stopping power with the density effect
                                  # (tables only: range and total stopping power change)
+FLAG_RAYLEIGH = 16               # Rayleigh scattering tabulated (mu_R > 0)
 
 E_ABS_E = 0.2                   # MeV
 E_ABS_G = 0.05                  # MeV
@@ -123,6 +126,48 @@ def mu_compton(m: Material, e: float) -> float:
 
 def mu_photo(m: Material, e: float) -> float:
     return C_PE * m.p / e ** 3
+
+
+def rayleigh_b_coeff(m: Material) -> float:
+    """b / E^2 of the Rayleigh form factor (MeV^-2): with the screening radius
+    a = 0.885 a0 Z_s^(-1/3) and k = E / (hbar c), b = 2 (k a)^2, and
+    q^2 a^2 = b (1 - cos)."""
+    a = 0.885 * A0 * m.zs ** (-1.0 / 3.0)
+    return 2.0 * a * a / (HBARC * HBARC)
+
+
+def rayleigh_integral_quad(b: float) -> float:
+    """I(b) = int_{-1}^{1} (1 + c^2) (1 + b (1 - c))^-4 dc by adaptive
+    quadrature in s = 1 - c (break points where the form factor falls)."""
+    pts = [p for p in (0.1 / b, 1.0 / b, 10.0 / b) if 0.0 < p < 2.0] if b > 0 else None
+    f = lambda s: (1.0 + (1.0 - s) ** 2) * (1.0 + b * s) ** -4
+    val, _ = integrate.quad(f, 0.0, 2.0, points=pts, epsabs=0.0, epsrel=1e-12, limit=400)
+    return val
+
+
+def rayleigh_integral_closed(b: float) -> float:
+    """The same integral in closed form: with v = 1 + b s the integrand is a
+    sum of powers of v, so I = [G(v)] from v = 1 to 1 + 2b over b, with
+    G(v) = -(2/3 + 2/(3b) + 1/(3b^2)) v^-3 + (1/b + 1/b^2) v^-2 - v^-1 / b^2.
+    Exact, but it cancels for small b."""
+    def g(v):
+        return (-(2.0 / 3.0 + 2.0 / (3.0 * b) + 1.0 / (3.0 * b * b)) / v ** 3
+                + (1.0 / b + 1.0 / (b * b)) / v ** 2 - 1.0 / (b * b * v))
+    return (g(1.0 + 2.0 * b) - g(1.0)) / b
+
+
+def rayleigh_integral(b: float) -> float:
+    """I(b): quadrature where the form factor is broad, closed form where it
+    is sharp (b >= 1)."""
+    return rayleigh_integral_closed(b) if b >= 1.0 else rayleigh_integral_quad(b)
+
+
+def mu_rayleigh(m: Material, e: float) -> float:
+    """Coherent scattering of the Z electrons of each atom: per atom
+    dsigma/dOmega = (r_e^2 / 2)(1 + cos^2) Z^2 F(q)^2 with the screened form
+    factor F = (1 + q^2 a^2)^-2; per gram N_A B pi r_e^2 I(b).  As E -> 0 it
+    tends to Z^2 times the Thomson cross section."""
+    return N_A * m.b * math.pi * R_E ** 2 * rayleigh_integral(rayleigh_b_coeff(m) * e * e)
 
 
 def mu_pair(m: Material, e: float) -> float:
@@ -303,7 +348,9 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
                   bremsstrahlung photons and pair leptons at forward-peaked
                   angles instead of along their parent;
       "density"   standard, with the density effect in the collision stopping
-                  power (and so in the range).
+                  power (and so in the range);
+      "rayleigh"  standard, with Rayleigh scattering tabulated;
+      "refined"   every refinement above: angular, density, rayleigh.
     """
     e = energy_grid()
     n_mat = len(materials)
@@ -317,6 +364,10 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
         flags |= FLAG_ANGULAR
     elif variant == "density":
         flags |= FLAG_DENSITY
+    elif variant == "rayleigh":
+        flags |= FLAG_RAYLEIGH
+    elif variant == "refined":
+        flags |= FLAG_ANGULAR | FLAG_DENSITY | FLAG_RAYLEIGH
     elif variant != "standard":
         raise ValueError(f"unknown table variant {variant!r}")
     w_cc = None if flags & FLAG_NO_HARD else E_ABS_E
@@ -330,6 +381,8 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
             if not flags & FLAG_PE_ONLY:
                 data[mi, Q_MU_C, i] = mu_compton(m, ei)
                 data[mi, Q_MU_PP, i] = mu_pair(m, ei)
+                if flags & FLAG_RAYLEIGH:
+                    data[mi, Q_MU_R, i] = mu_rayleigh(m, ei)
             data[mi, Q_MU_PE, i] = mu_photo(m, ei)
             data[mi, Q_LAMBDA1_INV, i] = lambda1_inv(m, ei)
             if not flags & FLAG_NO_HARD:
@@ -370,7 +423,7 @@ def read_blob(blob: bytes) -> Tables:
     (magic, ver, n_mat, n_e, n_q, emin, emax, eae, eag, wcc, wcr, ks, fe, ah, flags,
      _) = _HDR.unpack_from(blob, 0)
     if magic != BLOB_MAGIC or ver != BLOB_VERSION or n_e != N_E or n_q != N_Q:
-        raise ValueError("not a version-1 table blob")
+        raise ValueError("not a version-2 table blob")
     off = _HDR.size
     mats, data = [], np.empty((n_mat, n_q, n_e))
     for mi in range(n_mat):

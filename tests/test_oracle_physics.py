@@ -72,6 +72,33 @@ def test_interaction_branching_ratios(blob, e, m):
         assert abs(phat - pk) <= 4 * math.sqrt(pk * (1 - pk) / len(inter)) + 1e-9, (code, phat, pk)
 
 
+@pytest.mark.parametrize("e,m", [(0.02, T.MAT_WATER), (0.03, T.MAT_BONE), (0.08, T.MAT_BONE)])
+def test_rayleigh_branching_and_attenuation(e, m):
+    """Rayleigh flag: coherent scattering is a fourth real interaction; the
+    first one happens at depth distributed as exp(-(mu_C + mu_pe + mu_pp + mu_R) z)
+    and its kind follows mu_C : mu_pe : mu_pp : mu_R."""
+    blob = T.standard_blob("rayleigh")
+    rho = 1.85 if m == T.MAT_BONE else 1.0
+    ph = phantoms.homogeneous(8, 8, 400, 0.5, material=m, density=rho)
+    x, y = ph.centre_xy()
+    n = 100_000
+    z, kind = oracle.first_interaction(blob, ph, sources.pencil(PHOTON, e, x + 0.1, y + 0.1), n,
+                                       seed=17, kinds=True)
+    mat = T.MATERIALS[m]
+    mus = np.array([T.mu_compton(mat, e), T.mu_photo(mat, e), T.mu_pair(mat, e), T.mu_rayleigh(mat, e)])
+    p = mus / mus.sum()
+    assert p[3] > 0.005
+    inter = kind[kind != 6]
+    for code, pk in zip((2, 3, 4, 8), p):
+        phat = np.mean(inter == code)
+        assert abs(phat - pk) <= 4 * math.sqrt(pk * (1 - pk) / len(inter)) + 1e-9, (code, phat, pk)
+    mu = rho * mus.sum()
+    for depth in (0.5 / mu, 1.0 / mu, 2.0 / mu):
+        q = math.exp(-mu * depth)
+        qhat = np.mean(z > depth)
+        assert abs(qhat - q) <= 4 * math.sqrt(q * (1 - q) / n), (depth, qhat, q)
+
+
 def test_photoabsorption_only_layer_deposits(blob):
     """Photoabsorption-only tables, 0.1 MeV photons (photoelectrons below the
     electron cutoff are absorbed on the spot): the energy deposited in layer
@@ -202,6 +229,38 @@ def quad_mean(pdf):
     num = integrate.quad(lambda x: (1 - x) * pdf(x), -1, 1, limit=200, points=[0.999, 0.99999])[0]
     den = integrate.quad(pdf, -1, 1, limit=200, points=[0.999, 0.99999])[0]
     return num / den
+
+
+@pytest.mark.parametrize("e,m", [(0.02, T.MAT_WATER), (0.1, T.MAT_BONE), (1.0, T.MAT_WATER)])
+def test_rayleigh_angles_follow_screened_thomson(e, m):
+    """Rayleigh polar angle: density (1 + c^2) (1 + b (1 - c))^-4 with
+    b = 2 (k a)^2, k = E / (hbar c), a = 0.885 a0 Z_s^(-1/3) (the form factor
+    of an exponentially screened atom), integrated per bin by quadrature."""
+    blob = T.standard_blob("rayleigh")
+    c = oracle.sample(blob, 6 + m, e, 300_000, seed=26)[:, 0]
+    b = T.rayleigh_b_coeff(T.MATERIALS[m]) * e * e
+    pdf = lambda x: (1 + x * x) / (1 + b * (1 - x)) ** 4
+    edges = np.unique(np.concatenate([np.linspace(-1, 1, 41), 1 - np.geomspace(1e-6, 1, 40)]))
+    pb = np.array([integrate.quad(pdf, a_, b_)[0] for a_, b_ in zip(edges[:-1], edges[1:])])
+    pb /= pb.sum()
+    assert c.min() >= -1 and c.max() <= 1
+    assert _chi2_pvalue(np.histogram(c, edges)[0], pb) > 1e-3
+
+
+def test_rayleigh_flag_conserves_energy_and_changes_only_photon_paths(blob):
+    """Rayleigh flag: energy still balances; the source draws are unchanged; a
+    pure Rayleigh-free run (standard tables) differs."""
+    ph = phantoms.homogeneous(16, 16, 16, 1.0)
+    src = sources.point_field(PHOTON, *ph.centre_xy(), 100.0, 3.0, 3.0, energy=0.2)
+    a = oracle.simulate(blob, ph, src, 3000, seed=82)
+    b = oracle.simulate(T.standard_blob("refined"), ph, src, 3000, seed=82)
+    for r in (a, b):
+        bal = r["bal"]
+        closed = bal["E_csda"] + bal["E_local"] + bal["E_esc"] + bal["E_miss"]
+        assert abs(closed - bal["E_src"]) <= 1e-9 * bal["E_src"]
+    assert a["bal"]["E_src"] == b["bal"]["E_src"]
+    assert a["cnt"]["rayleigh"] == 0 and b["cnt"]["rayleigh"] > 0
+    assert not np.array_equal(a["S"], b["S"])
 
 
 def test_angular_flag_keeps_energy_and_draw_structure(blob):

@@ -151,7 +151,7 @@ def test_range_is_monotone_and_density_scaled_materials_match(tabs):
 
 def test_blob_roundtrip_and_validation(blob):
     t = T.read_blob(blob)
-    assert t.data.shape == (4, 8, 512)
+    assert t.data.shape == (4, T.N_Q, 512)
     assert T.write_blob(t) == blob
     assert oracle.blob_check(blob) == 4
     assert oracle.blob_check(blob[:-8]) == -1
@@ -169,7 +169,7 @@ def test_blob_roundtrip_and_validation(blob):
 
 def test_oracle_interpolation_matches_nodes_and_is_linear_in_log_e(blob, tabs):
     e = tabs.energies
-    for q in range(8):
+    for q in range(T.N_Q):
         for i in (0, 17, 255, 511):
             assert oracle.interp(blob, 2, q, e[i]) == pytest.approx(tabs.data[2, q, i], rel=1e-12, abs=1e-300)
     # midpoint in ln E is the mean of the two nodes
@@ -258,3 +258,39 @@ def test_density_effect_only_lowers_high_energy_losses():
     r_std, r_den = std.data[T.MAT_WATER, T.Q_RANGE], den.data[T.MAT_WATER, T.Q_RANGE]
     assert r_den[-1] > r_std[-1]
     np.testing.assert_array_equal(std.data[:, T.Q_MU_C], den.data[:, T.Q_MU_C])
+
+
+# ------------------------------------------------------------ Rayleigh
+
+@pytest.mark.parametrize("b", [1.0, 2.5, 10.0, 300.0, 1e4])
+def test_rayleigh_integral_closed_form_matches_quadrature(b):
+    """The closed form of int_0^2 (1 + (1 - s)^2) (1 + b s)^-4 ds (partial
+    fractions in v = 1 + b s) against adaptive quadrature."""
+    assert T.rayleigh_integral_closed(b) == pytest.approx(T.rayleigh_integral_quad(b), rel=1e-9)
+
+
+def test_rayleigh_limits():
+    """Small b (E -> 0): the form factor is 1 and the integral is int (1 + c^2) dc
+    = 8/3, so mu_R -> N_A (sum w Z^2 / A) sigma_Thomson with sigma_T = 8 pi r_e^2 / 3.
+    Large b: the integral tends to 2 / (3 b)."""
+    assert T.rayleigh_integral(1e-9) == pytest.approx(8 / 3, rel=1e-8)
+    for b in (1e4, 1e6):
+        assert b * T.rayleigh_integral(b) == pytest.approx(2 / 3, rel=3 / b ** 0.5)
+    sigma_t = 8 * math.pi * T.R_E ** 2 / 3
+    for m in T.MATERIALS:
+        assert T.mu_rayleigh(m, 1e-7) == pytest.approx(T.N_A * m.b * sigma_t, rel=1e-6)
+        # falls monotonically with energy
+        e = np.geomspace(0.001, 20, 60)
+        mu = np.array([T.mu_rayleigh(m, x) for x in e])
+        assert np.all(np.diff(mu) < 0)
+
+
+def test_rayleigh_tables_only_in_flagged_blobs():
+    std = T.read_blob(T.standard_blob())
+    ray = T.read_blob(T.standard_blob("rayleigh"))
+    assert np.all(std.data[:, T.Q_MU_R] == 0)
+    assert np.all(ray.data[:, T.Q_MU_R] > 0)
+    other = [q for q in range(T.N_Q) if q != T.Q_MU_R]
+    np.testing.assert_array_equal(std.data[:, other], ray.data[:, other])
+    assert ray.flags == T.FLAG_RAYLEIGH
+    assert oracle.blob_check(T.standard_blob("refined")) == 4
