@@ -235,18 +235,24 @@ def main():
         f"10x10 field N_1%={n1f} at {n1f / tf:.3e} hist/s")
     line["electron_20MeV"] = electron
 
-    # ------------------------------------------------------------ angular tables
-    tha = eng.load_materials(tables.standard_blob("angular"))
-    ang = {}
-    for w, n in ((wg, 20_000_000), (we, 4_000_000)):
-        pa = eng.load_phantom(w.phantom, tha)
-        eng.simulate(pa, w.source, n, w.seed, n_vox=w.phantom.n_vox)
-        ta_, ra_ = timed(lambda: eng.simulate(pa, w.source, n, w.seed, n_vox=w.phantom.n_vox), 2)
-        ang[w.name] = {"histories": n, "hist_per_s": n / ta_, "kernel_hist_per_s": n / (ra_["kernel_ms"] * 1e-3)}
-        eng.unload_phantom(pa)
-    eng.unload_materials(tha)
-    line["angular_tables"] = ang
-    log(f"angular tables: {ang}")
+    # ------------------------------------------------------------ table variants
+    # physics refinements behind table flags: emission angles, the density
+    # effect, Rayleigh scattering, and all three together
+    variants = {}
+    for variant in ("angular", "density", "rayleigh", "refined"):
+        thv = eng.load_materials(tables.standard_blob(variant))
+        cur = {}
+        for w, n in ((wg, 20_000_000), (we, 4_000_000)):
+            pa = eng.load_phantom(w.phantom, thv)
+            eng.simulate(pa, w.source, n, w.seed, n_vox=w.phantom.n_vox)
+            ta_, ra_ = timed(lambda: eng.simulate(pa, w.source, n, w.seed, n_vox=w.phantom.n_vox), 2)
+            cur[w.name] = {"histories": n, "hist_per_s": n / ta_,
+                           "kernel_hist_per_s": n / (ra_["kernel_ms"] * 1e-3)}
+            eng.unload_phantom(pa)
+        eng.unload_materials(thv)
+        variants[variant] = cur
+    line["table_variants"] = variants
+    log(f"table variants: {variants}")
 
     # ------------------------------------------------------------ paper geometry
     from paper_0910_0329_amd.inputs.sources import ELECTRON, PHOTON

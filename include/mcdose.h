@@ -102,7 +102,9 @@ enum {
      * electron segment, hard event) the iterations that ran it and the lanes
      * that took part */
     MCD_C_ITERS, MCD_C_LIVE, MCD_C_IT_FETCH, MCD_C_IT_PHOTON, MCD_C_IT_ELECTRON, MCD_C_IT_HARD,
-    MCD_C_LN_FETCH, MCD_C_LN_PHOTON, MCD_C_LN_ELECTRON, MCD_C_LN_HARD, MCD_NCOUNT = 40
+    MCD_C_LN_FETCH, MCD_C_LN_PHOTON, MCD_C_LN_ELECTRON, MCD_C_LN_HARD,
+    MCD_C_RAYLEIGH,  /* coherent scatterings (tables with the Rayleigh flag) */
+    MCD_NCOUNT = 40
 };
 
 /* Per-history diagnostic record (mcd_opts.history_records). */
@@ -191,10 +193,18 @@ int mcd_create(int device, uint64_t hbm_budget_bytes, mcd_ctx** out);
 int mcd_destroy(mcd_ctx* ctx);
 
 /* Loads a physics table blob (cross sections per interaction, material and
- * energy, Sec. 2.2; format: magic "MCDTAB\0\1", version 1, 512-node log grid
- * from 1 keV to 20 MeV, 8 quantities per material).  The blob is validated
+ * energy, Sec. 2.2; format: magic "MCDTAB\0\1", version 3, 512-node log grid
+ * from 1 keV to 20 MeV, 10 quantities per material, at most 8 materials).
+ * Header flags select physics refinements beyond the paper's scheme:
+ *   4  emission angles (Sauter photoelectrons, forward-peaked bremsstrahlung
+ *      photons and pair leptons),  8  density effect (tables only),
+ *   16 Rayleigh scattering (mu_R tabulated),
+ *   32 hinge angles matching the second Lewis moment (from lambda2);
+ * 1 and 2 mark test tables.  Other bits are rejected.  The blob is validated
  * (sizes, monotone ranges, non-negative finite values, scalar ranges) and
- * converted to FP32 device tables.  *out_tables receives a handle. */
+ * converted to FP32 device tables.  *out_tables receives a handle; the blob
+ * stays the caller's.  Errors: MCD_E_INVAL for a malformed blob, MCD_E_NOMEM
+ * past the HBM budget. */
 int mcd_load_materials(mcd_ctx* ctx, const void* blob, size_t nbytes, int32_t* out_tables);
 int mcd_unload_materials(mcd_ctx* ctx, int32_t tables);
 

@@ -34,15 +34,17 @@
 #define MC2 0.51099895              /* MeV */
 #define MEV_PER_G_TO_GY 1.602176634e-10
 #define NE 512
-#define NQ 9
+#define NQ 10
 #define A0 5.29177210903e-9         /* Bohr radius, cm */
 #define HBARC 1.973269804e-11       /* MeV cm */
 
-enum { Q_MUC, Q_MUPE, Q_MUPP, Q_R, Q_L1INV, Q_SM, Q_SB, Q_LR, Q_MUR };
+enum { Q_MUC, Q_MUPE, Q_MUPP, Q_R, Q_L1INV, Q_SM, Q_SB, Q_LR, Q_MUR, Q_L2INV };
 enum { PHOTON = 0, ELECTRON = 1, POSITRON = 2 };
 /* Blob flag: emission angles of photoelectrons (Sauter), bremsstrahlung
  * photons and pair leptons instead of their parent's direction. */
 #define FLAG_ANGULAR 4u
+/* Blob flag: the hinge angle matches the second Lewis moment as well. */
+#define FLAG_HINGE2 32u
 
 /* ------------------------------------------------------------------ Philox */
 
@@ -93,7 +95,7 @@ static int load_tables(const void* blob, size_t nbytes, tables* t)
 {
     const unsigned char* b = (const unsigned char*)blob;
     if (!blob || nbytes < HDR_BYTES || memcmp(b, "MCDTAB\0\1", 8) != 0) return -1;
-    if (rd_u32(b + 8) != 2 || rd_u32(b + 16) != NE || rd_u32(b + 20) != NQ) return -1;
+    if (rd_u32(b + 8) != 3 || rd_u32(b + 16) != NE || rd_u32(b + 20) != NQ) return -1;
     int n_mat = (int)rd_u32(b + 12);
     if (n_mat < 1 || n_mat > 255 || nbytes != (size_t)HDR_BYTES + (size_t)n_mat * MAT_BYTES)
         return -1;
@@ -451,6 +453,77 @@ static double sample_hinge_cos(stream* s, double a)
 {
     double u = uni(s);
     double mu = a * u / (1.0 + a - u);
+    return 1.0 - 2.0 * mu;
+}
+
+/* Second-moment hinge.  After a step of kappa transport mean free paths the
+ * Lewis moments of the deflection are <P1> = exp(-kappa) and
+ * <P2> = exp(-kappa r), r = lambda1 / lambda2; in mu = (1 - cos)/2 (with
+ * 1 - P2 = 6 mu (1 - mu)) that is
+ *   m1 = <mu>   = (1 - exp(-kappa)) / 2,
+ *   m2 = <mu^2> = m1 - (1 - exp(-kappa r)) / 6.
+ * The first-moment Wentzel law (screening a1) fixes m1 only.  With
+ * t = m2 / m1 and q(A) = <mu^2>_A / <mu>_A of the Wentzel law, increasing in A:
+ *   t >= q(a1)  heavier tail: mixture (1 - B) delta(mu) + B Wentzel(A), with
+ *               q(A) = t and B = m1 / <mu>_A;
+ *   t <  q(a1)  lighter tail: Wentzel(A) compressed to [0, S], mu = S mu_A,
+ *               with <mu>_A^2 / <mu^2>_A = m1^2 / m2 and S = t / q(A).
+ * Either way mu = S * A u' / (1 + A - u') with u' = u / B when u < B, else
+ * mu = 0: one uniform, as for the first-moment hinge.  If no root lies in
+ * [a1, 1e3] the first-moment law is kept (A = a1, B = S = 1). */
+static double wentzel_m1(double a) { return a * ((1.0 + a) * log1p(1.0 / a) - 1.0); }
+static double wentzel_m2(double a)
+{
+    return a * ((1.0 + 2.0 * a) - 2.0 * a * (1.0 + a) * log1p(1.0 / a));
+}
+static double wentzel_q(double a) { return wentzel_m2(a) / wentzel_m1(a); }
+static double wentzel_f(double a) { double m = wentzel_m1(a); return m * m / wentzel_m2(a); }
+
+/* root of g(A) = target on [lo, hi] for increasing g, by bisection in ln A;
+ * returns 0 if the target is not bracketed */
+static int solve_increasing(double (*g)(double), double target, double lo, double hi, double* out)
+{
+    if (!(g(lo) <= target && g(hi) >= target)) return 0;
+    for (int it = 0; it < 200 && hi / lo - 1.0 > 1e-15; ++it) {
+        double mid = sqrt(lo * hi);
+        if (g(mid) < target) lo = mid;
+        else hi = mid;
+    }
+    *out = sqrt(lo * hi);
+    return 1;
+}
+
+static void hinge2_params(double kappa, double a1, double r, double* A, double* B, double* S)
+{
+    double m1 = -0.5 * expm1(-kappa);
+    double m2 = m1 + expm1(-kappa * r) / 6.0;
+    *A = a1;
+    *B = 1.0;
+    *S = 1.0;
+    if (!(m2 > m1 * m1) || !(m2 < m1)) return;
+    double t = m2 / m1;
+    double a;
+    if (t >= wentzel_q(a1)) {
+        if (solve_increasing(wentzel_q, t, a1, 1e3, &a)) {
+            *A = a;
+            *B = m1 / wentzel_m1(a);
+        }
+    } else if (solve_increasing(wentzel_f, m1 * m1 / m2, a1, 1e3, &a)) {
+        *A = a;
+        *S = t / wentzel_q(a);
+    }
+}
+
+static double sample_hinge2_cos(stream* s, double kappa, double a1, double r)
+{
+    double A, B, S;
+    hinge2_params(kappa, a1, r, &A, &B, &S);
+    double u = uni(s);
+    double mu = 0.0;
+    if (u < B) {
+        u /= B;
+        mu = S * A * u / (1.0 + A - u);
+    }
     return 1.0 - 2.0 * mu;
 }
 
@@ -813,7 +886,14 @@ static void transport_electron(ctx* c, stream* s, int type, double T, double r[3
         if (lim == LIM_K) {
             if (before) {
                 c->cnt[ORC_C_HINGES]++;
-                double cost = sample_hinge_cos(s, t->a_hinge);
+                double cost;
+                if (t->flags & FLAG_HINGE2) {
+                    /* lambda1 / lambda2 at the energy the hinge is reached with */
+                    double r = interp(t, tab(t, m, Q_L2INV), T) / interp(t, tab(t, m, Q_L1INV), T);
+                    cost = sample_hinge2_cos(s, t->kappa_step, t->a_hinge, r);
+                } else {
+                    cost = sample_hinge_cos(s, t->a_hinge);
+                }
                 double phi = 2.0 * PI * uni(s);
                 rotate(d, cost, phi);
                 kap = (1.0 - xi) * t->kappa_step;
@@ -1062,7 +1142,8 @@ int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n,
 {
     tables t;
     if (load_tables(blob, nbytes, &t)) return -1;
-    if (which < 0 || which >= 6 + t.n_mat || !(e > 0.0) || !out) { free(t.q); return -1; }
+    int ok = (which >= 0 && which < 6 + t.n_mat) || (which >= 256 && which < 256 + t.n_mat);
+    if (!ok || !(e > 0.0) || !out) { free(t.q); return -1; }
     if (which == 1 && !(e > 2.0 * t.w_cc)) { free(t.q); return -1; }
     if (which == 2 && !(e > t.w_cr)) { free(t.q); return -1; }
     for (uint64_t i = 0; i < n; ++i) {
@@ -1106,6 +1187,11 @@ int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n,
             o[0] = sample_sauter_cos(&s, e);
         } else if (which == 5) {
             o[0] = sample_forward_cos(&s, e);
+        } else if (which >= 256) {
+            int m = which - 256;
+            double r = interp(&t, tab(&t, m, Q_L2INV), e) / interp(&t, tab(&t, m, Q_L1INV), e);
+            o[0] = sample_hinge2_cos(&s, t.kappa_step, t.a_hinge, r);
+            o[1] = r;
         } else if (which >= 6) {
             o[0] = sample_rayleigh_cos(&s, t.ray_b[which - 6] * e * e);
         } else {

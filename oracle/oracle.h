@@ -114,7 +114,9 @@ int orc_first_interaction(const void* blob, size_t nbytes, const orc_grid* g,
  *   which 4  Sauter photoelectron angle at kinetic energy e: cos(theta)
  *   which 5  forward emission angle (bremsstrahlung photon, pair lepton) for
  *            an emitter of kinetic energy e: cos(theta)
- *   which 6+m  Rayleigh angle at photon energy e in material m: cos(theta)    */
+ *   which 6+m  Rayleigh angle at photon energy e in material m: cos(theta)
+ *   which 256+m  second-moment hinge at electron energy e in material m:
+ *            cos(theta), lambda1/lambda2                                      */
 int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n, uint32_t seed,
                double* out);
 

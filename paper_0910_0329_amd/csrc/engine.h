@@ -15,7 +15,8 @@ constexpr int kRec = 48;          // bytes per stacked or queued particle
 constexpr int kBatches = 16;      // sub-tallies of the batch-statistics tally (power of two)
 
 // Device-side tables of one material set (FP32, converted from the FP64 blob).
-//   phot[m*512 + i] = (mu_C/rho, mu_pe/rho, mu_pp/rho, 0)   cm^2/g
+//   phot[m*512 + i] = (mu_C/rho, mu_pe/rho, mu_pp/rho, mu_R/rho)   cm^2/g
+//   (mu_R, coherent scattering, is zero unless the tables carry it)
 //   elec[m*512 + i] = (R, 1/(lambda1 rho), Sigma_M/rho, Sigma_B/rho)
 struct DevTables {
     float4* phot;
@@ -29,6 +30,9 @@ struct DevTables {
     float e_abs_e, e_abs_g, w_cc, w_cr, kappa_step, f_e, a_hinge;
     float f_shift;          // log2(1 - f_e) / (log2 step): (1 - f_e) E is this many nodes below E
     int angular;            // 1: emission angles for photoelectrons, brems photons, pair leptons
+    float ray_b[kMaxMat];   // Rayleigh form-factor scale: b = ray_b[m] E^2 (1/MeV^2)
+    const float4* hinge;    // [m*512 + i] = (A, B, S, 0) of the second-moment hinge law
+    int hinge2;             // 1: hinge angles from the second-moment law
 };
 
 // Source descriptor as the kernels see it.

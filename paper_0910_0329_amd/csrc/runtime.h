@@ -40,15 +40,17 @@ constexpr size_t kSmallBytes = (kOffRed + 24 + 63) / 64 * 64;
 static_assert(kOffCnt >= 8 * kBal, "energy balance overlaps the counters");
 static_assert(kSmallBytes % 64 == 0 && kOffRed + 24 <= kSmallBytes, "small block layout");
 
+constexpr int kNQ = 10;           // tabulated quantities per material in a table blob
+
 struct TableSet {
     DevTables dev{};
-    std::vector<double> q;           // FP64 nodes [n_mat][8][512] (for majorants)
+    std::vector<double> q;           // FP64 nodes [n_mat][kNQ][512] (ranges, majorants)
     int n_mat = 0;
     double emin = 0, emax = 0, e_abs_e = 0, e_abs_g = 0, w_cc = 0, w_cr = 0;
     double kappa_step = 0, f_e = 0, a_hinge = 0;
-    size_t bytes = 0;
+    size_t bytes = 0;                // each of the three device arrays phot, elec, hinge
     bool live = false;
-    const double* range(int m) const { return &q[((size_t)m * 8 + 3) * kNE]; }
+    const double* range(int m) const { return &q[((size_t)m * kNQ + 3) * kNE]; }
 };
 
 struct PhantomRec {
@@ -121,6 +123,33 @@ namespace mcd {
 int run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_graph, hipStream_t s);
 // Records per particle queue for cycles of `chunk` new histories.
 unsigned int queue_capacity(uint64_t chunk);
+
+// Mutex that hands itself over in request order (a ticket lock).  The serving
+// worker takes the device lock once per epoch and asks for it again at once;
+// with a plain mutex it can win every time and hold off a blocking call for
+// the whole backlog.  Usable with std::lock_guard.
+class FairMutex {
+public:
+    void lock()
+    {
+        std::unique_lock<std::mutex> lk(m_);
+        const uint64_t t = next_++;
+        cv_.wait(lk, [&] { return serving_ == t; });
+    }
+    void unlock()
+    {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            ++serving_;
+        }
+        cv_.notify_all();
+    }
+
+private:
+    std::mutex m_;
+    std::condition_variable cv_;
+    uint64_t next_ = 0, serving_ = 0;
+};
 }  // namespace mcd
 
 struct mcd_ctx {
@@ -131,7 +160,7 @@ struct mcd_ctx {
     uint64_t budget = 0, used = 0;
     // Lock order: run_mu, then mu, then the server's mutex.
     std::mutex mu;        // tables / phantoms vectors (changed under run_mu and mu)
-    std::mutex run_mu;    // one device run (blocking call or serving epoch) at a time
+    mcd::FairMutex run_mu;  // one device run (blocking call or serving epoch) at a time, FIFO
     std::mutex mu_alloc;  // budget accounting
     std::vector<mcd::TableSet> tables;
     std::vector<mcd::PhantomRec> phantoms;

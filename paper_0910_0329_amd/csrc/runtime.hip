@@ -153,8 +153,9 @@ int mcd_destroy(mcd_ctx* c)
     c->shutdown_serving();
     for (auto& t : c->tables)
         if (t.live) {
-            c->release(t.dev.phot, t.bytes / 2);
-            c->release(t.dev.elec, t.bytes / 2);
+            c->release(t.dev.phot, t.bytes);
+            c->release(t.dev.elec, t.bytes);
+            c->release((void*)t.dev.hinge, t.bytes);
         }
     for (auto& p : c->phantoms)
         if (p.live) {
@@ -191,13 +192,67 @@ namespace {
 
 constexpr size_t kHdr = 8 + 4 * 4 + 9 * 8 + 2 * 4;
 constexpr size_t kMatHdr = 16 + 6 * 8;
-constexpr int kNQ = 8;
+constexpr double kBohr = 5.29177210903e-9;    // cm
+constexpr double kHbarC = 1.973269804e-11;    // MeV cm
 
 template <class T> T rd(const unsigned char* p)
 {
     T v;
     std::memcpy(&v, p, sizeof v);
     return v;
+}
+
+// Second-moment hinge law.  A step of kappa transport mean free paths has
+// Lewis moments <mu> = (1 - e^-kappa)/2 and
+// <mu^2> = <mu> - (1 - e^(-kappa r))/6 in mu = (1 - cos)/2, r = lambda1/lambda2.
+// The law is  mu = S A v / (1 + A - v),  v = u / B, when the uniform u < B,
+// and mu = 0 otherwise: a Wentzel law of screening A, either mixed with no
+// deflection (B < 1, S = 1: a heavier tail than the first-moment Wentzel law
+// a1) or compressed to [0, S] (S < 1, B = 1: a lighter tail).  A comes from
+// a bisection in ln A on [a1, 1e3]; without a root the first-moment law
+// (a1, 1, 1) is kept.
+struct WentzelMoments {
+    double m1, m2;
+    explicit WentzelMoments(double a)
+    {
+        const double l = std::log1p(1.0 / a);
+        m1 = a * ((1.0 + a) * l - 1.0);
+        m2 = a * ((1.0 + 2.0 * a) - 2.0 * a * (1.0 + a) * l);
+    }
+};
+
+template <class F> bool bisect_log(F f, double target, double lo, double hi, double& x)
+{
+    if (f(lo) > target || f(hi) < target) return false;
+    while (hi / lo - 1.0 > 1e-15) {
+        const double mid = std::sqrt(lo * hi);
+        if (mid <= lo || mid >= hi) break;
+        (f(mid) < target ? lo : hi) = mid;
+    }
+    x = std::sqrt(lo * hi);
+    return true;
+}
+
+float4 hinge_law(double kappa, double a1, double r)
+{
+    const double m1 = -0.5 * std::expm1(-kappa);
+    const double m2 = m1 + std::expm1(-kappa * r) / 6.0;
+    float4 out = make_float4((float)a1, 1.f, 1.f, 0.f);
+    if (!(m2 > m1 * m1 && m2 < m1)) return out;
+    const double t = m2 / m1;
+    auto ratio = [](double a) { WentzelMoments w(a); return w.m2 / w.m1; };
+    auto spread = [](double a) { WentzelMoments w(a); return w.m1 * w.m1 / w.m2; };
+    double a;
+    if (t >= ratio(a1)) {
+        if (bisect_log(ratio, t, a1, 1e3, a)) {
+            out.x = (float)a;
+            out.y = (float)(m1 / WentzelMoments(a).m1);
+        }
+    } else if (bisect_log(spread, m1 * m1 / m2, a1, 1e3, a)) {
+        out.x = (float)a;
+        out.z = (float)(t / ratio(a));
+    }
+    return out;
 }
 
 // Interpolant of a node array, linear in ln E (FP64, host side).
@@ -220,7 +275,7 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
         return c->fail(MCD_E_INVAL, "table blob: bad magic or size");
     const uint32_t ver = rd<uint32_t>(b + 8), n_mat = rd<uint32_t>(b + 12);
     const uint32_t n_e = rd<uint32_t>(b + 16), n_q = rd<uint32_t>(b + 20);
-    if (ver != 1 || n_e != (uint32_t)kNE || n_q != (uint32_t)kNQ)
+    if (ver != 3 || n_e != (uint32_t)kNE || n_q != (uint32_t)kNQ)
         return c->fail(MCD_E_INVAL, "table blob: unsupported version or grid");
     if (n_mat < 1 || n_mat > (uint32_t)kMaxMat)
         return c->fail(MCD_E_INVAL, "table blob: 1 to 8 materials supported");
@@ -239,7 +294,7 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
     ts.f_e = rd<double>(s + 56);
     ts.a_hinge = rd<double>(s + 64);
     const uint32_t flags = rd<uint32_t>(s + 72);
-    if (flags & ~15u) return c->fail(MCD_E_INVAL, "table blob: unknown flags");
+    if (flags & ~63u) return c->fail(MCD_E_INVAL, "table blob: unknown flags");
     if (!(ts.emin > 0 && ts.emax > ts.emin && ts.e_abs_e > ts.emin && ts.e_abs_e < ts.emax &&
           ts.e_abs_g > ts.emin && ts.e_abs_g < ts.emax && ts.w_cc > 0 && ts.w_cr > 0 &&
           ts.kappa_step > 0 && ts.f_e > 0 && ts.f_e < 1 && ts.a_hinge > 0))
@@ -257,29 +312,40 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
             if (!(r[i] > r[i - 1])) return c->fail(MCD_E_INVAL, "table blob: range not increasing");
     }
     // FP32 device layout: float4 per node for the photon and electron groups
-    std::vector<float4> ph((size_t)n_mat * kNE), el((size_t)n_mat * kNE);
+    // and for the second-moment hinge law (left zero unless the blob asks)
+    const bool hinge2 = (flags & 32u) != 0;
+    std::vector<float4> ph((size_t)n_mat * kNE), el((size_t)n_mat * kNE), hl((size_t)n_mat * kNE);
     for (uint32_t m = 0; m < n_mat; ++m)
         for (int i = 0; i < kNE; ++i) {
             const double* q = &ts.q[(size_t)m * kNQ * kNE];
             ph[m * kNE + i] = make_float4((float)q[0 * kNE + i], (float)q[1 * kNE + i],
-                                          (float)q[2 * kNE + i], 0.f);
+                                          (float)q[2 * kNE + i], (float)q[8 * kNE + i]);
             el[m * kNE + i] = make_float4((float)q[3 * kNE + i], (float)q[4 * kNE + i],
                                           (float)q[5 * kNE + i], (float)q[6 * kNE + i]);
+            hl[m * kNE + i] = hinge2 && q[4 * kNE + i] > 0.0
+                                  ? hinge_law(ts.kappa_step, ts.a_hinge, q[9 * kNE + i] / q[4 * kNE + i])
+                                  : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     (void)hipSetDevice(c->device);
-    ts.bytes = 2 * ph.size() * sizeof(float4);
-    int rc = c->alloc((void**)&ts.dev.phot, ts.bytes / 2, "tables");
+    ts.bytes = ph.size() * sizeof(float4);
+    float4* hinge_dev = nullptr;
+    int rc = c->alloc((void**)&ts.dev.phot, ts.bytes, "tables");
     if (rc) return rc;
-    rc = c->alloc((void**)&ts.dev.elec, ts.bytes / 2, "tables");
+    rc = c->alloc((void**)&ts.dev.elec, ts.bytes, "tables");
+    if (!rc) rc = c->alloc((void**)&hinge_dev, ts.bytes, "tables");
     if (rc) {
-        c->release(ts.dev.phot, ts.bytes / 2);
+        c->release(ts.dev.phot, ts.bytes);
+        c->release(ts.dev.elec, ts.bytes);
         return rc;
     }
-    hipError_t e = hipMemcpy(ts.dev.phot, ph.data(), ts.bytes / 2, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ts.dev.elec, el.data(), ts.bytes / 2, hipMemcpyHostToDevice);
+    ts.dev.hinge = hinge_dev;
+    hipError_t e = hipMemcpy(ts.dev.phot, ph.data(), ts.bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ts.dev.elec, el.data(), ts.bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(hinge_dev, hl.data(), ts.bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        c->release(ts.dev.phot, ts.bytes / 2);
-        c->release(ts.dev.elec, ts.bytes / 2);
+        c->release(ts.dev.phot, ts.bytes);
+        c->release(ts.dev.elec, ts.bytes);
+        c->release(hinge_dev, ts.bytes);
         return c->hip_fail(e, "table upload");
     }
     DevTables& d = ts.dev;
@@ -298,10 +364,24 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
     d.kappa_step = (float)ts.kappa_step;
     d.f_e = (float)ts.f_e;
     d.angular = (flags & 4u) ? 1 : 0;
+    d.hinge2 = hinge2 ? 1 : 0;
+    // Rayleigh angular law of an exponentially screened atom: screening
+    // radius a = 0.885 a0 Z_s^(-1/3), Z_s = B / (Z/A) from the material
+    // header (rho, Z/A, I, B, ...); b = 2 (a E / hbar c)^2
+    for (int m = 0; m < kMaxMat; ++m) {
+        d.ray_b[m] = 0.f;
+        if (m >= (int)n_mat) continue;
+        const unsigned char* mh = b + kHdr + m * mat_bytes + 16;
+        const double zoa = rd<double>(mh + 8), bz = rd<double>(mh + 24);
+        if (zoa > 0.0 && bz > 0.0) {
+            const double a = 0.885 * kBohr * std::cbrt(zoa / bz);
+            d.ray_b[m] = (float)(2.0 * a * a / (kHbarC * kHbarC));
+        }
+    }
     d.f_shift = (float)(std::log2(1.0 - ts.f_e) * (kNE - 1) / std::log2(ts.emax / ts.emin));
     d.a_hinge = (float)ts.a_hinge;
     ts.live = true;
-    std::lock_guard<std::mutex> run(c->run_mu);
+    std::lock_guard<mcd::FairMutex> run(c->run_mu);
     std::lock_guard<std::mutex> g(c->mu);
     c->tables.push_back(std::move(ts));
     *out_tables = (int32_t)c->tables.size() - 1;
@@ -311,7 +391,7 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
 int mcd_unload_materials(mcd_ctx* c, int32_t t)
 {
     if (!c) return MCD_E_INVAL;
-    std::lock_guard<std::mutex> run(c->run_mu);
+    std::lock_guard<mcd::FairMutex> run(c->run_mu);
     std::lock_guard<std::mutex> g(c->mu);
     if (t < 0 || t >= (int32_t)c->tables.size() || !c->tables[t].live) return MCD_E_NOTFOUND;
     for (auto& p : c->phantoms)
@@ -319,8 +399,9 @@ int mcd_unload_materials(mcd_ctx* c, int32_t t)
     TableSet& ts = c->tables[t];
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    c->release(ts.dev.phot, ts.bytes / 2);
-    c->release(ts.dev.elec, ts.bytes / 2);
+    c->release(ts.dev.phot, ts.bytes);
+    c->release(ts.dev.elec, ts.bytes);
+    c->release((void*)ts.dev.hinge, ts.bytes);
     ts.live = false;
     ts.q.clear();
     return MCD_OK;
@@ -332,7 +413,7 @@ int mcd_load_phantom(mcd_ctx* c, const mcd_grid* g, const uint8_t* mat, const fl
                      int32_t tables, int32_t* out_phantom)
 {
     if (!c || !g || !mat || !rho || !out_phantom) return MCD_E_INVAL;
-    std::lock_guard<std::mutex> run(c->run_mu);
+    std::lock_guard<mcd::FairMutex> run(c->run_mu);
     if (tables < 0 || tables >= (int32_t)c->tables.size() || !c->tables[tables].live)
         return c->fail(MCD_E_NOTFOUND, "unknown table handle");
     if (g->nx < 1 || g->ny < 1 || g->nz < 1 || !(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0) ||
@@ -353,14 +434,14 @@ int mcd_load_phantom(mcd_ctx* c, const mcd_grid* g, const uint8_t* mat, const fl
         rmax[mat[v]] = std::max(rmax[mat[v]], (double)rho[v]);
     }
     // Woodcock majorant at the nodes: max over present materials of
-    // rho_max * (mu_C + mu_pe + mu_pp) per gram, rounded up to FP32.
+    // rho_max * (mu_C + mu_pe + mu_pp + mu_R) per gram, rounded up to FP32.
     std::vector<float> maj(kNE);
     for (int i = 0; i < kNE; ++i) {
         double best = 0.0;
         for (int m = 0; m < ts.n_mat; ++m) {
             if (rmax[m] <= 0.0) continue;
             const double* q = &ts.q[(size_t)m * kNQ * kNE];
-            best = std::max(best, rmax[m] * (q[i] + q[kNE + i] + q[2 * kNE + i]));
+            best = std::max(best, rmax[m] * (q[i] + q[kNE + i] + q[2 * kNE + i] + q[8 * kNE + i]));
         }
         float f = (float)best;
         if ((double)f < best) f = std::nextafter(f, INFINITY);
@@ -395,7 +476,7 @@ int mcd_load_phantom(mcd_ctx* c, const mcd_grid* g, const uint8_t* mat, const fl
 int mcd_unload_phantom(mcd_ctx* c, int32_t ph)
 {
     if (!c) return MCD_E_INVAL;
-    std::lock_guard<std::mutex> run(c->run_mu);
+    std::lock_guard<mcd::FairMutex> run(c->run_mu);
     std::lock_guard<std::mutex> g(c->mu);
     if (ph < 0 || ph >= (int32_t)c->phantoms.size() || !c->phantoms[ph].live) return MCD_E_NOTFOUND;
     if (c->serving_uses(ph)) return c->fail(MCD_E_BUSY, "phantom has queued or admitted requests");

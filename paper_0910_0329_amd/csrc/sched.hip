@@ -592,7 +592,7 @@ int mcd_simulate(mcd_ctx* c, int32_t phantom, const mcd_source* src, uint64_t n_
                  void* hip_stream)
 {
     if (!c || !out) return MCD_E_INVAL;
-    std::lock_guard<std::mutex> run_lock(c->run_mu);
+    std::lock_guard<mcd::FairMutex> run_lock(c->run_mu);
     if (!phantom_ok(c, phantom)) return c->fail(MCD_E_NOTFOUND, "unknown phantom handle");
     const uint64_t first = opts ? opts->first_history : 0;
     if (n_histories == 0 || n_histories >= ((uint64_t)1 << 32) || seed >= ((uint64_t)1 << 32) ||
@@ -641,7 +641,7 @@ int mcd_simulate_batch(mcd_ctx* c, int32_t phantom, const mcd_batch_item* items,
                        uint64_t seed, const mcd_opts* opts, mcd_result* total, void* hip_stream)
 {
     if (!c || !items || n_items < 1 || n_items > kMaxBatch) return MCD_E_INVAL;
-    std::lock_guard<std::mutex> run_lock(c->run_mu);
+    std::lock_guard<mcd::FairMutex> run_lock(c->run_mu);
     if (!phantom_ok(c, phantom)) return c->fail(MCD_E_NOTFOUND, "unknown phantom handle");
     if (opts && (opts->kernel != MCD_KERNEL_REGROUPED || opts->accumulate))
         return c->fail(MCD_E_INVAL, "batches run on the regrouped kernel without accumulation");

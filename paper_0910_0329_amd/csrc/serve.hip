@@ -395,7 +395,7 @@ static void serve_loop(mcd_ctx* c)
             });
             if (S->stop) return;
         }
-        std::lock_guard<std::mutex> run(c->run_mu);
+        std::lock_guard<mcd::FairMutex> run(c->run_mu);
         admit(c, S);
         run_epoch(c, S);
     }

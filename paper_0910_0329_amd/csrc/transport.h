@@ -32,7 +32,7 @@ constexpr float kInf = __builtin_huge_valf();
 enum { PHOTON = 0, ELECTRON = 1, POSITRON = 2, DEAD = -1 };
 enum { LIM_E, LIM_H, LIM_K, LIM_B, LIM_F };
 // Event codes of the per-particle hash (diagnostics).
-enum { EV_VIRTUAL = 1, EV_COMPTON, EV_PHOTO, EV_PAIR, EV_PAIR_VOID, EV_G_ESCAPE, EV_G_ABSORB,
+enum { EV_VIRTUAL = 1, EV_COMPTON, EV_PHOTO, EV_PAIR, EV_PAIR_VOID, EV_G_ESCAPE, EV_G_ABSORB, EV_RAYLEIGH,
        EV_SEG = 10, EV_MOLLER = 20, EV_BREMS, EV_MOLLER_VOID, EV_E_ESCAPE };
 
 DEV float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
@@ -135,6 +135,7 @@ struct Env {
     const float4* elec;      // LDS [n_mat * 512]
     const float* maj;        // LDS [512]
     const float* r_abs;      // LDS [kMaxMat]
+    const float* ray_b;      // LDS [kMaxMat]
     uint32_t seed, key;      // Philox key of the particle being transported
 };
 
@@ -370,6 +371,25 @@ struct Transport {
         }
     }
 
+    // Rayleigh polar angle: p(c) ~ (1 + c^2) (1 + b (1 - c))^-4, the Thomson
+    // law times the squared form factor of an exponentially screened atom.
+    // s = 1 - c comes from (1 + b s)^-4 on [0, 2] by inverting its CDF,
+    // (1 + b s)^-3 = 1 - u (1 - (1 + 2b)^-3), and is accepted with
+    // probability (1 + c^2) / 2.  Two uniforms per try.  Photons above the
+    // absorption energy have b > 1, where the base-2 forms below lose at most
+    // a few ulp of 1 in c.
+    DEV float rayleigh_cos(Part& q, float b)
+    {
+        const float w = 1.f - exp2f(-3.f * __log2f(1.f + 2.f * b));
+        const float ib = __builtin_amdgcn_rcpf(b);
+        for (;;) {
+            const float u = uni(q);
+            const float s = fminf((exp2f(__log2f(1.f - u * w) * (-1.f / 3.f)) - 1.f) * ib, 2.f);
+            const float c = 1.f - s;
+            if (uni(q) <= 0.5f * (1.f + c * c)) return c;
+        }
+    }
+
     // ---------------------------------------------------------- rotation
     // Rotates (u, v, w) by polar cosine cost and azimuth (cos, sin) = (cp, sph).
     DEV static void rotate(float& u, float& v, float& w, float cost, float cp, float sph)
@@ -509,6 +529,7 @@ struct Transport {
         const float mu_c = rho * (a.x + (b.x - a.x) * fr);
         const float mu_pe = rho * (a.y + (b.y - a.y) * fr);
         const float mu_pp = rho * (a.z + (b.z - a.z) * fr);
+        const float mu_r = rho * (a.w + (b.w - a.w) * fr);
         const float xs = uni(q) * mu_max;
         if (xs < mu_c) {
             ev(EV_COMPTON);
@@ -557,6 +578,13 @@ struct Transport {
                 ev(EV_PAIR_VOID);
                 count(MCD_C_VOID);
             }
+        } else if (xs < mu_c + mu_pe + mu_pp + mu_r) {
+            // coherent: same energy, new direction
+            ev(EV_RAYLEIGH);
+            count(MCD_C_RAYLEIGH);
+            const float cost = rayleigh_cos(q, env.ray_b[m] * q.e * q.e);
+            const float ph = uni(q);
+            rotate(q.u, q.v, q.w, cost, __builtin_amdgcn_cosf(ph), __builtin_amdgcn_sinf(ph));
         } else {
             ev(EV_VIRTUAL);
             count(MCD_C_VIRTUAL);
@@ -690,8 +718,24 @@ struct Transport {
             if (q.before) {
                 count(MCD_C_HINGES);
                 const float u = uni(q);
-                const float A = g.t.a_hinge;
-                const float mu = fdiv(A * u, 1.f + A - u);
+                float mu;
+                if (g.t.hinge2) {
+                    // second-moment law at the energy the hinge is reached
+                    // with: no deflection when u >= B, else a Wentzel angle
+                    // of screening A compressed by S
+                    int j;
+                    float fj;
+                    eidx(q.e, j, fj);
+                    const float4 h0 = g.t.hinge[m * kNE + j], h1 = g.t.hinge[m * kNE + j + 1];
+                    const float A = h0.x + (h1.x - h0.x) * fj;
+                    const float B = h0.y + (h1.y - h0.y) * fj;
+                    const float S = h0.z + (h1.z - h0.z) * fj;
+                    const float v = fminf(fdiv(u, B), 1.f);
+                    mu = u < B ? S * fdiv(A * v, 1.f + A - v) : 0.f;
+                } else {
+                    const float A = g.t.a_hinge;
+                    mu = fdiv(A * u, 1.f + A - u);
+                }
                 const float ph = uni(q);
                 rotate(q.u, q.v, q.w, 1.f - 2.f * mu, __builtin_amdgcn_cosf(ph),
                        __builtin_amdgcn_sinf(ph));
@@ -879,7 +923,7 @@ struct Transport {
 };
 
 // Stages the material tables and the majorant into LDS (dynamic shared memory
-// laid out as phot | elec | maj | r_abs | extra floats).
+// laid out as phot | elec | maj | r_abs | ray_b | extra floats).
 DEV void stage_tables(const KGeom& g, float4* lds, Env& env, float** extra)
 {
     const int nt = g.t.n_mat * kNE;
@@ -887,17 +931,22 @@ DEV void stage_tables(const KGeom& g, float4* lds, Env& env, float** extra)
     float4* s_elec = lds + nt;
     float* s_maj = (float*)(lds + 2 * nt);
     float* s_rabs = s_maj + kNE;
+    float* s_rayb = s_rabs + kMaxMat;
     for (int i = threadIdx.x; i < nt; i += blockDim.x) {
         s_phot[i] = g.t.phot[i];
         s_elec[i] = g.t.elec[i];
     }
     for (int i = threadIdx.x; i < kNE; i += blockDim.x) s_maj[i] = g.maj[i];
-    for (int i = threadIdx.x; i < kMaxMat; i += blockDim.x) s_rabs[i] = g.t.r_abs[i];
+    for (int i = threadIdx.x; i < kMaxMat; i += blockDim.x) {
+        s_rabs[i] = g.t.r_abs[i];
+        s_rayb[i] = g.t.ray_b[i];
+    }
     env.phot = s_phot;
     env.elec = s_elec;
     env.maj = s_maj;
     env.r_abs = s_rabs;
-    *extra = s_rabs + kMaxMat;
+    env.ray_b = s_rayb;
+    *extra = s_rayb + kMaxMat;
 }
 
 }  // namespace mcd

@@ -21,6 +21,7 @@ Quantities per material, per gram (the order is the blob's quantity index):
   7  L_r/rho      restricted total stopping power              MeV cm^2/g
   8  mu_R/rho     Rayleigh (coherent) scattering, screened     cm^2/g
                   Thomson law (zero unless the tables enable it)
+  9  1/(lambda2 rho)  second transport cross section (elastic)   cm^2/g
 
 Absorption energies are 200 keV (electrons) and 50 keV (photons) (Sec. 3);
 the production thresholds W_cc and W_cr are taken equal to them.
@@ -51,13 +52,14 @@ K_B = 5.07e-3                   # cm^2 / g, bremsstrahlung
 N_E = 512
 E_MIN = 1.0e-3                  # MeV
 E_MAX = 20.0                    # MeV
-N_Q = 9
+N_Q = 10
 
-Q_MU_C, Q_MU_PE, Q_MU_PP, Q_RANGE, Q_LAMBDA1_INV, Q_SIGMA_M, Q_SIGMA_B, Q_L_R, Q_MU_R = range(9)
-QUANTITY_NAMES = ("mu_C", "mu_pe", "mu_pp", "R", "lambda1_inv", "Sigma_M", "Sigma_B", "L_r", "mu_R")
+Q_MU_C, Q_MU_PE, Q_MU_PP, Q_RANGE, Q_LAMBDA1_INV, Q_SIGMA_M, Q_SIGMA_B, Q_L_R, Q_MU_R, Q_LAMBDA2_INV = range(10)
+QUANTITY_NAMES = ("mu_C", "mu_pe", "mu_pp", "R", "lambda1_inv", "Sigma_M", "Sigma_B", "L_r", "mu_R",
+                  "lambda2_inv")
 
 BLOB_MAGIC = b"MCDTAB\x00\x01"
-BLOB_VERSION = 2
+BLOB_VERSION = 3
 FLAG_NO_HARD = 1                 # test variant: Sigma_M = Sigma_B = 0, unrestricted losses
 FLAG_PE_ONLY = 2                 # test variant: photons interact only by photoabsorption
 FLAG_ANGULAR = 4                 # emission angles of photoelectrons, bremsstrahlung photons
@@ -65,6 +67,7 @@ FLAG_ANGULAR = 4                 # emission angles of photoelectrons, bremsstrah
 FLAG_DENSITY = 8                 # collision stopping power with the density effect
                                  # (tables only: range and total stopping power change)
 FLAG_RAYLEIGH = 16               # Rayleigh scattering tabulated (mu_R > 0)
+FLAG_HINGE2 = 32                 # hinge angle matches the second Lewis moment too
 
 E_ABS_E = 0.2                   # MeV
 E_ABS_G = 0.05                  # MeV
@@ -288,6 +291,16 @@ def lambda1_inv(m: Material, t: float) -> float:
     return N_A * m.ee * 2.0 * math.pi * k * (math.log1p(1.0 / a) - 1.0 / (1.0 + a))
 
 
+def lambda2_inv(m: Material, t: float) -> float:
+    """Second transport cross section per gram of the same model,
+    int (1 - P2(cos)) dsigma: with mu = (1 - cos)/2, 1 - P2 = 6 mu (1 - mu) and
+    int_0^1 6 mu (1 - mu) / (mu + a)^2 dmu = 6 [(1 + 2a) ln(1 + 1/a) - 2]."""
+    _, pc, beta2 = _kin(t)
+    a = screening_moliere(m, t)
+    k = (R_E * MC2 / (math.sqrt(beta2) * pc)) ** 2
+    return N_A * m.ee * 2.0 * math.pi * k * 3.0 * ((1.0 + 2.0 * a) * math.log1p(1.0 / a) - 2.0)
+
+
 def solve_a_hinge(kappa_step: float) -> float:
     """Screening A of the hinge's Wentzel angle whose mean mu equals the Lewis
     first moment of a step of kappa_step transport mean free paths:
@@ -350,7 +363,9 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
       "density"   standard, with the density effect in the collision stopping
                   power (and so in the range);
       "rayleigh"  standard, with Rayleigh scattering tabulated;
-      "refined"   every refinement above: angular, density, rayleigh.
+      "hinge2"    standard tables; the hinge angle matches the second Lewis
+                  moment exp(-s/lambda2) as well as the first;
+      "refined"   every refinement above: angular, density, rayleigh, hinge2.
     """
     e = energy_grid()
     n_mat = len(materials)
@@ -366,8 +381,10 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
         flags |= FLAG_DENSITY
     elif variant == "rayleigh":
         flags |= FLAG_RAYLEIGH
+    elif variant == "hinge2":
+        flags |= FLAG_HINGE2
     elif variant == "refined":
-        flags |= FLAG_ANGULAR | FLAG_DENSITY | FLAG_RAYLEIGH
+        flags |= FLAG_ANGULAR | FLAG_DENSITY | FLAG_RAYLEIGH | FLAG_HINGE2
     elif variant != "standard":
         raise ValueError(f"unknown table variant {variant!r}")
     w_cc = None if flags & FLAG_NO_HARD else E_ABS_E
@@ -385,6 +402,7 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
                     data[mi, Q_MU_R, i] = mu_rayleigh(m, ei)
             data[mi, Q_MU_PE, i] = mu_photo(m, ei)
             data[mi, Q_LAMBDA1_INV, i] = lambda1_inv(m, ei)
+            data[mi, Q_LAMBDA2_INV, i] = lambda2_inv(m, ei)
             if not flags & FLAG_NO_HARD:
                 data[mi, Q_SIGMA_M, i] = sigma_moller_hard(m, ei, E_ABS_E)
                 data[mi, Q_SIGMA_B, i] = sigma_brems_hard(m, ei, E_ABS_G)
@@ -423,7 +441,7 @@ def read_blob(blob: bytes) -> Tables:
     (magic, ver, n_mat, n_e, n_q, emin, emax, eae, eag, wcc, wcr, ks, fe, ah, flags,
      _) = _HDR.unpack_from(blob, 0)
     if magic != BLOB_MAGIC or ver != BLOB_VERSION or n_e != N_E or n_q != N_Q:
-        raise ValueError("not a version-2 table blob")
+        raise ValueError(f"not a version-{BLOB_VERSION} table blob")
     off = _HDR.size
     mats, data = [], np.empty((n_mat, n_q, n_e))
     for mi in range(n_mat):

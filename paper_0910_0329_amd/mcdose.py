@@ -21,7 +21,8 @@ COUNT_NAMES = ("histories", "flights", "virtual", "compton", "photo", "pair", "s
                "seg_E", "seg_h", "seg_k", "seg_b", "seg_f", "hinges", "moller", "brems",
                "spawns", "philox", "flushes", "escapes", "misses", "local", "void",
                "compton_tries", "moller_tries", "max_stack", "iters", "live", "it_fetch", "it_photon",
-               "it_electron", "it_hard", "ln_fetch", "ln_photon", "ln_electron", "ln_hard")
+               "it_electron", "it_hard", "ln_fetch", "ln_photon", "ln_electron", "ln_hard",
+               "rayleigh")
 
 
 class McdError(RuntimeError):

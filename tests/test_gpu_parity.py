@@ -208,6 +208,57 @@ def test_density_effect_tables_match_oracle(eng, kernel):
     eng.unload_materials(thd)
 
 
+@pytest.mark.parametrize("kernel", ("plain", "regrouped"))
+@pytest.mark.parametrize("variant,particle,e,n", [("rayleigh", PHOTON, 0.15, 60_000),
+                                                  ("refined", PHOTON, 0.25, 60_000),
+                                                  ("refined", PHOTON, 6.0, 30_000)])
+def test_rayleigh_tables_match_oracle(eng, variant, particle, e, n, kernel):
+    """Tables with the Rayleigh flag (alone, and with emission angles and the
+    density effect): coherent scattering as a fourth photon interaction."""
+    from paper_0910_0329_amd.inputs import tables
+    blob = tables.standard_blob(variant)
+    thr = eng.load_materials(blob)
+    ph = phantoms.random_field_phantom(40, 0.25, seed=55, nz=48)
+    x, y = ph.centre_xy()
+    src = sources.point_field(particle, x, y, 60.0, 3.0, 2.0, energy=e)
+    log(f"case {variant} tables particle={particle} e={e} n={n} kernel={kernel}")
+    g, ref = run_both(eng, blob, thr, ph, src, n, seed=19, key=6, kernel=kernel)
+    eng.unload_materials(thr)
+    check_dose(ph, g, ref, n, kernel)
+    check_balance(g, ref)
+    f = match_fraction(g, ref)
+    nr, nr_ref = g["cnt"]["rayleigh"], ref["cnt"]["rayleigh"]
+    log(f"  history match fraction {f:.4f}; Rayleigh events {nr} (oracle {nr_ref})")
+    assert f > 0.8
+    assert nr_ref > (200 if e < 1.0 else 5)
+    assert abs(nr - nr_ref) <= 0.05 * nr_ref + 10
+
+
+@pytest.mark.parametrize("kernel", ("plain", "regrouped"))
+@pytest.mark.parametrize("variant,particle,e,n", [("hinge2", ELECTRON, 12.0, 4_000),
+                                                  ("hinge2", PHOTON, 8.0, 30_000),
+                                                  ("refined", ELECTRON, 18.0, 3_000)])
+def test_second_moment_hinge_tables_match_oracle(eng, variant, particle, e, n, kernel):
+    """Tables with the hinge2 flag: hinge angles from the law matching both
+    Lewis moments (the device interpolates its per-node parameters, the
+    oracle solves for them at the hinge energy)."""
+    from paper_0910_0329_amd.inputs import tables
+    blob = tables.standard_blob(variant)
+    thh = eng.load_materials(blob)
+    ph = phantoms.random_field_phantom(40, 0.25, seed=56, nz=48)
+    x, y = ph.centre_xy()
+    src = sources.point_field(particle, x, y, 60.0, 3.0, 2.0, energy=e)
+    log(f"case {variant} tables particle={particle} e={e} n={n} kernel={kernel}")
+    g, ref = run_both(eng, blob, thh, ph, src, n, seed=23, key=8, kernel=kernel)
+    eng.unload_materials(thh)
+    check_dose(ph, g, ref, n, kernel)
+    check_balance(g, ref)
+    f = match_fraction(g, ref)
+    log(f"  history match fraction {f:.4f}; hinges {g['cnt']['hinges']} (oracle {ref['cnt']['hinges']})")
+    assert f > 0.8
+    assert g["cnt"]["hinges"] == pytest.approx(ref["cnt"]["hinges"], rel=0.02)
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_split_runs_and_repeatability(eng, th, kernel):
     w = configs.electron_20mev_wlw(4000)

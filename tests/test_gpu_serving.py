@@ -167,6 +167,32 @@ def test_cancel(eng, pool):
     assert st["queued"] == 0 and st["active"] == 0 and st["request_bytes"] == 0
 
 
+def test_blocking_call_is_not_starved_by_serving(eng, pool):
+    """The serving worker asks for the device again after every epoch; the
+    device lock goes to callers in request order, so a blocking run made
+    while a long request is served finishes long before that request."""
+    from paper_0910_0329_amd.mcdose import ADMITTED, E_CANCELED, McdError, RUNNING
+    pid, ph = pool[1]
+    g6 = g6mv(ph, 4.0)
+    eng.serve_configure(epoch_histories=50000, regroup=2)
+    log("case serve fairness")
+    big = eng.submit(pid, g6, 2_000_000_000, 3, 20)
+    deadline = time.time() + 10
+    while eng.poll(big)[1] == 0 and time.time() < deadline:
+        time.sleep(0.001)
+    t0 = time.perf_counter()
+    r = eng.simulate(pid, g6, 20_000, 3, 21, n_vox=ph.n_vox, regroup=2)
+    dt = time.perf_counter() - t0
+    st, done = eng.poll(big)
+    log(f"  blocking run took {dt * 1e3:.1f} ms while the request had {done} histories done")
+    assert st in (ADMITTED, RUNNING) and done < 2_000_000_000
+    assert r["dmax"] > 0
+    eng.cancel(big)
+    with pytest.raises(McdError) as ei:
+        eng.wait(big, n_vox=ph.n_vox)
+    assert ei.value.status == E_CANCELED
+
+
 def test_memory_limit_admission(eng, pool, th):
     """With room for one request at a time every request still completes, and
     one larger than the limit fails with NOMEM without disturbing the rest."""
@@ -202,7 +228,8 @@ def test_unload_busy_and_bad_tickets(eng, pool):
     pid, ph = pool[1]
     g6 = g6mv(ph, 4.0)
     eng.serve_configure(epoch_histories=50000, regroup=2)
-    t = eng.submit(pid, g6, 2_000_000, 5, 0)
+    log("case serve unload while busy")
+    t = eng.submit(pid, g6, 20_000_000, 5, 0)
     with pytest.raises(McdError) as ei:
         eng.unload_phantom(pid)
     assert ei.value.status == E_BUSY

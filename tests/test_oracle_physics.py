@@ -300,6 +300,48 @@ def test_hinge_reproduces_lewis_first_moment(tabs):
 
 # ------------------------------------------------------------ electrons
 
+@pytest.mark.parametrize("m,e", [(T.MAT_WATER, 0.3), (T.MAT_WATER, 5.0), (T.MAT_BONE, 1.0),
+                                 (T.MAT_BONE, 18.0)])
+def test_second_moment_hinge_reproduces_both_lewis_moments(m, e):
+    """hinge2 flag: after a step of kappa transport mean free paths the
+    deflection has <P1(cos)> = exp(-kappa) and <P2(cos)> = exp(-kappa r),
+    r = lambda1/lambda2 (Lewis); the hinge angle reproduces both.  The
+    first-moment hinge reproduces the first and misses the second by many
+    standard errors, so this pin tells the two apart."""
+    blob = T.standard_blob("hinge2")
+    n = 400_000
+    out = oracle.sample(blob, 256 + m, e, n, seed=27)
+    c, r = out[:, 0], out[0, 1]
+    mat = T.MATERIALS[m]
+    assert r == pytest.approx(T.lambda2_inv(mat, e) / T.lambda1_inv(mat, e), rel=1e-4)
+    k = T.KAPPA_STEP
+    assert c.min() >= -1 and c.max() <= 1
+    p1, p2 = c, 1.5 * c * c - 0.5
+    se = lambda x: x.std() / math.sqrt(n)
+    assert abs(p1.mean() - math.exp(-k)) <= 5 * se(p1)
+    assert abs(p2.mean() - math.exp(-k * r)) <= 5 * se(p2)
+    c1 = oracle.sample(blob, 3, e, n, seed=27)[:, 0]
+    q1, q2 = c1, 1.5 * c1 * c1 - 0.5
+    assert abs(q1.mean() - math.exp(-k)) <= 5 * se(q1)
+    assert abs(q2.mean() - math.exp(-k * r)) > 10 * se(q2)
+
+
+def test_second_moment_hinge_flag_keeps_energy_and_draws(blob):
+    """Same histories with and without the hinge2 flag: the source draws and
+    the energy balance hold, the dose changes."""
+    ph = phantoms.homogeneous(16, 16, 16, 1.0)
+    src = sources.pencil(ELECTRON, 12.0, *ph.centre_xy())
+    a = oracle.simulate(blob, ph, src, 1500, seed=83)
+    b = oracle.simulate(T.standard_blob("hinge2"), ph, src, 1500, seed=83)
+    for r in (a, b):
+        bal = r["bal"]
+        closed = bal["E_csda"] + bal["E_local"] + bal["E_esc"] + bal["E_miss"]
+        assert abs(closed - bal["E_src"]) <= 1e-9 * bal["E_src"]
+    assert a["bal"]["E_src"] == b["bal"]["E_src"]
+    assert b["cnt"]["hinges"] > 0
+    assert not np.array_equal(a["S"], b["S"])
+
+
 def test_csda_track_length_equals_range_difference():
     """No hard events: each electron's path length is (R(T0) - R(E_abs)) / rho,
     whatever its deflections and voxel crossings."""

@@ -113,6 +113,28 @@ def test_transport_cross_section_is_first_moment_of_wentzel_dcs():
         assert 1.0 / T.lambda1_inv(w, t) == pytest.approx(lam, rel=0.02)
 
 
+def test_second_transport_cross_section_against_quadrature():
+    """1/lambda2 = int (1 - P2(cos)) dsigma of the same screened-Rutherford
+    DCS, by quadrature in x = 1 - cos; lambda1/lambda2 tends to 3 (the
+    unscreened limit) from below as the screening vanishes."""
+    for w in (T.MATERIALS[T.MAT_WATER], T.MATERIALS[T.MAT_BONE]):
+        for t in (0.2, 1.0, 20.0):
+            _, pc, beta2 = T._kin(t)
+            a = T.screening_moliere(w, t)
+            k = (T.R_E * T.MC2 / (math.sqrt(beta2) * pc)) ** 2
+
+            def f(x):
+                c = 1.0 - x
+                return 2 * math.pi * (1.0 - 0.5 * (3 * c * c - 1)) * T.N_A * w.ee * k / (x + 2 * a) ** 2
+            val, _ = integrate.quad(f, 0.0, 2.0, points=[2 * a, 20 * a], epsrel=1e-11, limit=400)
+            assert T.lambda2_inv(w, t) == pytest.approx(val, rel=1e-8)
+            r = T.lambda2_inv(w, t) / T.lambda1_inv(w, t)
+            assert 2.0 < r < 3.0
+    w = T.MATERIALS[T.MAT_WATER]
+    rs = [T.lambda2_inv(w, t) / T.lambda1_inv(w, t) for t in (0.2, 1.0, 5.0, 20.0)]
+    assert np.all(np.diff(rs) > 0)
+
+
 def test_a_hinge_solves_lewis_first_moment():
     a = T.solve_a_hinge(0.1)
     assert a == pytest.approx(0.0143284, rel=1e-5)
