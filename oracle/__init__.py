@@ -21,7 +21,7 @@ BAL_NAMES = ("E_src", "E_csda", "E_local", "E_esc", "E_miss", "track_e")
 COUNT_NAMES = ("histories", "flights", "virtual", "compton", "photo", "pair", "segments",
                "seg_E", "seg_h", "seg_k", "seg_b", "seg_f", "hinges", "moller", "brems",
                "spawns", "philox", "flushes", "escapes", "misses", "local", "void",
-               "compton_tries", "moller_tries", "max_stack", "rayleigh")
+               "compton_tries", "moller_tries", "max_stack", "rayleigh", "bhabha")
 
 
 class Grid(C.Structure):

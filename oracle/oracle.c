@@ -34,17 +34,20 @@
 #define MC2 0.51099895              /* MeV */
 #define MEV_PER_G_TO_GY 1.602176634e-10
 #define NE 512
-#define NQ 10
+#define NQ 13
 #define A0 5.29177210903e-9         /* Bohr radius, cm */
 #define HBARC 1.973269804e-11       /* MeV cm */
 
-enum { Q_MUC, Q_MUPE, Q_MUPP, Q_R, Q_L1INV, Q_SM, Q_SB, Q_LR, Q_MUR, Q_L2INV };
+enum { Q_MUC, Q_MUPE, Q_MUPP, Q_R, Q_L1INV, Q_SM, Q_SB, Q_LR, Q_MUR, Q_L2INV, Q_RP, Q_SBH, Q_LRP };
 enum { PHOTON = 0, ELECTRON = 1, POSITRON = 2 };
 /* Blob flag: emission angles of photoelectrons (Sauter), bremsstrahlung
  * photons and pair leptons instead of their parent's direction. */
 #define FLAG_ANGULAR 4u
 /* Blob flag: the hinge angle matches the second Lewis moment as well. */
 #define FLAG_HINGE2 32u
+/* Blob flag: positrons take their own range (Q_RP) and hard Bhabha events
+ * (Q_SBH) in place of the electron range and Moller events. */
+#define FLAG_BHABHA 64u
 
 /* ------------------------------------------------------------------ Philox */
 
@@ -95,7 +98,7 @@ static int load_tables(const void* blob, size_t nbytes, tables* t)
 {
     const unsigned char* b = (const unsigned char*)blob;
     if (!blob || nbytes < HDR_BYTES || memcmp(b, "MCDTAB\0\1", 8) != 0) return -1;
-    if (rd_u32(b + 8) != 3 || rd_u32(b + 16) != NE || rd_u32(b + 20) != NQ) return -1;
+    if (rd_u32(b + 8) != 4 || rd_u32(b + 16) != NE || rd_u32(b + 20) != NQ) return -1;
     int n_mat = (int)rd_u32(b + 12);
     if (n_mat < 1 || n_mat > 255 || nbytes != (size_t)HDR_BYTES + (size_t)n_mat * MAT_BYTES)
         return -1;
@@ -124,11 +127,12 @@ static int load_tables(const void* blob, size_t nbytes, tables* t)
     }
     for (size_t i = 0; i < (size_t)n_mat * NQ * NE; ++i)
         if (!(t->q[i] >= 0.0) || !isfinite(t->q[i])) { free(t->q); return -1; }
-    for (int m = 0; m < n_mat; ++m) {
-        const double* r = t->q + ((size_t)m * NQ + Q_R) * NE;
-        for (int i = 1; i < NE; ++i)
-            if (!(r[i] > r[i - 1])) { free(t->q); return -1; }
-    }
+    for (int m = 0; m < n_mat; ++m)
+        for (int k = 0; k < 2; ++k) {
+            const double* r = t->q + ((size_t)m * NQ + (k ? Q_RP : Q_R)) * NE;
+            for (int i = 1; i < NE; ++i)
+                if (!(r[i] > r[i - 1])) { free(t->q); return -1; }
+        }
     return 0;
 }
 
@@ -387,6 +391,33 @@ static double sample_moller(stream* s, double t, double w_cc, uint64_t* cnt)
     }
 }
 
+/* Bhabha: fraction e = W / t given to the atomic electron, on [w_cc / t, 1],
+ * density ~ e^-2 [1 - b1 e + b2 e^2 - b3 e^3 + b4 e^4] with
+ *   b1 = a (2 (g + 1)^2 - 1) / (g^2 - 1),  b2 = a (3 (g + 1)^2 + 1) / (g + 1)^2,
+ *   b3 = a 2 g (g - 1) / (g + 1)^2,        b4 = a (g - 1)^2 / (g + 1)^2,
+ * a = ((g - 1) / g)^2, g the positron's Lorentz factor.  e is drawn from e^-2
+ * by inversion and accepted with the bracket (at most 1).  Two uniforms per
+ * try. */
+static double sample_bhabha(stream* s, double t, double w_cc, uint64_t* cnt)
+{
+    double e0 = w_cc / t;
+    double g = 1.0 + t / MC2;
+    double a = (g - 1.0) / g;
+    a *= a;
+    double gp = g + 1.0;
+    double b1 = a * (2.0 * gp * gp - 1.0) / (g * g - 1.0);
+    double b2 = a * (3.0 * gp * gp + 1.0) / (gp * gp);
+    double b3 = a * 2.0 * g * (g - 1.0) / (gp * gp);
+    double b4 = a * (g - 1.0) * (g - 1.0) / (gp * gp);
+    for (;;) {
+        double e = e0 / (1.0 - uni(s) * (1.0 - e0));
+        double ua = uni(s);
+        if (cnt) cnt[ORC_C_MOLLER_TRIES]++;
+        double br = 1.0 - e * (b1 - e * (b2 - e * (b3 - e * b4)));
+        if (ua <= br) return e;
+    }
+}
+
 /* Kramers-type bremsstrahlung: W = W_cr (T / W_cr)^u, a 1/W law on [W_cr, T]. */
 static double sample_brems(stream* s, double t, double w_cr)
 {
@@ -541,6 +572,7 @@ typedef struct {
     const geom* G;
     const double* mu_max;
     double r_abs[256];                 /* R(E_abs,e) per material */
+    double r_abs_pos[256];             /* the same on the positron range */
     uint32_t k0, k1;
     uint32_t h;
     /* tally: per-history accumulation flushed at history end */
@@ -561,7 +593,7 @@ static uint64_t hash_init(uint64_t lineage) { return (0xcbf29ce484222325ull ^ li
 static void hash_ev(uint64_t* hp, uint32_t code) { *hp = (*hp ^ code) * 0x100000001b3ull; }
 
 enum { EV_VIRTUAL = 1, EV_COMPTON, EV_PHOTO, EV_PAIR, EV_PAIR_VOID, EV_G_ESCAPE, EV_G_ABSORB, EV_RAYLEIGH,
-       EV_SEG = 10, EV_MOLLER = 20, EV_BREMS, EV_MOLLER_VOID, EV_E_ESCAPE };
+       EV_SEG = 10, EV_MOLLER = 20, EV_BREMS, EV_MOLLER_VOID, EV_E_ESCAPE, EV_BHABHA, EV_BHABHA_VOID };
 
 static void deposit(ctx* c, size_t v, double e, int channel)
 {
@@ -796,16 +828,21 @@ static void transport_electron(ctx* c, stream* s, int type, double T, double r[3
     double xi = uni(s);
     double kap = xi * t->kappa_step;
     int before = 1;
+    /* with the Bhabha flag a positron takes its own range and hard Bhabha
+     * events; otherwise it shares the electron's quantities */
+    const int bhabha = type == POSITRON && (t->flags & FLAG_BHABHA);
+    const int q_r = bhabha ? Q_RP : Q_R, q_s = bhabha ? Q_SBH : Q_SM;
+    const double* r_abs = bhabha ? c->r_abs_pos : c->r_abs;
     for (;;) {
         size_t v = lin_voxel(G, idx);
         int m = G->mat[v];
         double rho = G->rho[v];
-        const double* R = tab(t, m, Q_R);
+        const double* R = tab(t, m, q_r);
         double rt = interp(t, R, T);
         double lam = interp(t, tab(t, m, Q_L1INV), T);
-        double sh = interp(t, tab(t, m, Q_SM), T) + interp(t, tab(t, m, Q_SB), T);
+        double sh = interp(t, tab(t, m, q_s), T) + interp(t, tab(t, m, Q_SB), T);
         /* the five step limits, ties resolved in the order E, h, kappa, b, f */
-        double l_e = fmax(0.0, (rt - c->r_abs[m]) / rho);
+        double l_e = fmax(0.0, (rt - r_abs[m]) / rho);
         double l_h = sh > 0.0 ? fmax(0.0, n_h / (rho * sh)) : INFINITY;
         double l_k = fmax(0.0, kap / (rho * lam));
         int axis;
@@ -841,17 +878,23 @@ static void transport_electron(ctx* c, stream* s, int type, double T, double r[3
             return;
         }
         if (lim == LIM_H) {
-            double sm = interp(t, tab(t, m, Q_SM), T);
+            double sm = interp(t, tab(t, m, q_s), T);
             double sb = interp(t, tab(t, m, Q_SB), T);
             if (uni(s) * (sm + sb) < sm) {
-                if (T <= 2.0 * t->w_cc) {
-                    /* interpolation tail below the Moller threshold: no event */
+                /* inelastic: Moller for electrons (the primary keeps the
+                 * larger share, W <= T/2); with the Bhabha flag, Bhabha for
+                 * positrons (the atomic electron may take any W <= T).  Both
+                 * particles leave at the two-body angles. */
+                double w_min = bhabha ? t->w_cc : 2.0 * t->w_cc;
+                if (T <= w_min) {
+                    /* interpolation tail below the threshold: no event */
                     c->cnt[ORC_C_VOID]++;
-                    hash_ev(ph, EV_MOLLER_VOID);
+                    hash_ev(ph, bhabha ? EV_BHABHA_VOID : EV_MOLLER_VOID);
                 } else {
-                    c->cnt[ORC_C_MOLLER]++;
-                    hash_ev(ph, EV_MOLLER);
-                    double eps = sample_moller(s, T, t->w_cc, c->cnt);
+                    c->cnt[bhabha ? ORC_C_BHABHA : ORC_C_MOLLER]++;
+                    hash_ev(ph, bhabha ? EV_BHABHA : EV_MOLLER);
+                    double eps = bhabha ? sample_bhabha(s, T, t->w_cc, c->cnt)
+                                        : sample_moller(s, T, t->w_cc, c->cnt);
                     double phi = 2.0 * PI * uni(s);
                     double w = eps * T;
                     double cs = sqrt(w * (T + 2.0 * MC2) / (T * (w + 2.0 * MC2)));
@@ -1021,7 +1064,10 @@ int orc_simulate(const void* blob, size_t nbytes, const orc_grid* g, const uint8
     c.t = &t;
     c.G = &G;
     c.mu_max = mu_max;
-    for (int m = 0; m < t.n_mat; ++m) c.r_abs[m] = interp(&t, tab(&t, m, Q_R), t.e_abs_e);
+    for (int m = 0; m < t.n_mat; ++m) {
+        c.r_abs[m] = interp(&t, tab(&t, m, Q_R), t.e_abs_e);
+        c.r_abs_pos[m] = interp(&t, tab(&t, m, Q_RP), t.e_abs_e);
+    }
     c.k0 = seed;
     c.k1 = request_key;
     c.S = S;
@@ -1142,7 +1188,8 @@ int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n,
 {
     tables t;
     if (load_tables(blob, nbytes, &t)) return -1;
-    int ok = (which >= 0 && which < 6 + t.n_mat) || (which >= 256 && which < 256 + t.n_mat);
+    int ok = (which >= 0 && which < 6 + t.n_mat) || (which >= 256 && which < 256 + t.n_mat) ||
+             which == 512;
     if (!ok || !(e > 0.0) || !out) { free(t.q); return -1; }
     if (which == 1 && !(e > 2.0 * t.w_cc)) { free(t.q); return -1; }
     if (which == 2 && !(e > t.w_cr)) { free(t.q); return -1; }
@@ -1187,6 +1234,8 @@ int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n,
             o[0] = sample_sauter_cos(&s, e);
         } else if (which == 5) {
             o[0] = sample_forward_cos(&s, e);
+        } else if (which == 512) {
+            o[0] = e > t.w_cc ? sample_bhabha(&s, e, t.w_cc, NULL) : 0.0;
         } else if (which >= 256) {
             int m = which - 256;
             double r = interp(&t, tab(&t, m, Q_L2INV), e) / interp(&t, tab(&t, m, Q_L1INV), e);

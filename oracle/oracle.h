@@ -52,7 +52,7 @@ enum {
     ORC_C_SEGMENTS, ORC_C_SEG_E, ORC_C_SEG_H, ORC_C_SEG_K, ORC_C_SEG_B, ORC_C_SEG_F,
     ORC_C_HINGES, ORC_C_MOLLER, ORC_C_BREMS, ORC_C_SPAWNS, ORC_C_PHILOX, ORC_C_FLUSHES,
     ORC_C_ESCAPES, ORC_C_MISSES, ORC_C_LOCAL, ORC_C_VOID, ORC_C_COMPTON_TRIES,
-    ORC_C_MOLLER_TRIES, ORC_C_MAX_STACK, ORC_C_RAYLEIGH, ORC_NCOUNT = 32
+    ORC_C_MOLLER_TRIES, ORC_C_MAX_STACK, ORC_C_RAYLEIGH, ORC_C_BHABHA, ORC_NCOUNT = 32
 };
 
 /* Optional per-history record: total deposited energy, total electron track
@@ -116,7 +116,9 @@ int orc_first_interaction(const void* blob, size_t nbytes, const orc_grid* g,
  *            an emitter of kinetic energy e: cos(theta)
  *   which 6+m  Rayleigh angle at photon energy e in material m: cos(theta)
  *   which 256+m  second-moment hinge at electron energy e in material m:
- *            cos(theta), lambda1/lambda2                                      */
+ *            cos(theta), lambda1/lambda2
+ *   which 512  Bhabha event of a positron of kinetic energy e: fraction of e
+ *            given to the electron                                            */
 int orc_sample(const void* blob, size_t nbytes, int which, double e, uint64_t n, uint32_t seed,
                double* out);
 

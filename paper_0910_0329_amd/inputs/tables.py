@@ -22,6 +22,11 @@ Quantities per material, per gram (the order is the blob's quantity index):
   8  mu_R/rho     Rayleigh (coherent) scattering, screened     cm^2/g
                   Thomson law (zero unless the tables enable it)
   9  1/(lambda2 rho)  second transport cross section (elastic)   cm^2/g
+ 10  R+           restricted CSDA range of positrons            g/cm^2
+ 11  Sigma_Bh/rho hard Bhabha cross section (W > W_cc)         cm^2/g
+ 12  L_r+/rho     restricted total stopping power of positrons  MeV cm^2/g
+                  (10-12 are used when the tables enable Bhabha scattering;
+                  otherwise positrons take the electron quantities)
 
 Absorption energies are 200 keV (electrons) and 50 keV (photons) (Sec. 3);
 the production thresholds W_cc and W_cr are taken equal to them.
@@ -52,14 +57,15 @@ K_B = 5.07e-3                   # cm^2 / g, bremsstrahlung
 N_E = 512
 E_MIN = 1.0e-3                  # MeV
 E_MAX = 20.0                    # MeV
-N_Q = 10
+N_Q = 13
 
-Q_MU_C, Q_MU_PE, Q_MU_PP, Q_RANGE, Q_LAMBDA1_INV, Q_SIGMA_M, Q_SIGMA_B, Q_L_R, Q_MU_R, Q_LAMBDA2_INV = range(10)
+(Q_MU_C, Q_MU_PE, Q_MU_PP, Q_RANGE, Q_LAMBDA1_INV, Q_SIGMA_M, Q_SIGMA_B, Q_L_R, Q_MU_R, Q_LAMBDA2_INV,
+ Q_RANGE_POS, Q_SIGMA_BH, Q_L_R_POS) = range(13)
 QUANTITY_NAMES = ("mu_C", "mu_pe", "mu_pp", "R", "lambda1_inv", "Sigma_M", "Sigma_B", "L_r", "mu_R",
-                  "lambda2_inv")
+                  "lambda2_inv", "R_pos", "Sigma_Bh", "L_r_pos")
 
 BLOB_MAGIC = b"MCDTAB\x00\x01"
-BLOB_VERSION = 3
+BLOB_VERSION = 4
 FLAG_NO_HARD = 1                 # test variant: Sigma_M = Sigma_B = 0, unrestricted losses
 FLAG_PE_ONLY = 2                 # test variant: photons interact only by photoabsorption
 FLAG_ANGULAR = 4                 # emission angles of photoelectrons, bremsstrahlung photons
@@ -68,6 +74,7 @@ FLAG_DENSITY = 8                 # collision stopping power with the density eff
                                  # (tables only: range and total stopping power change)
 FLAG_RAYLEIGH = 16               # Rayleigh scattering tabulated (mu_R > 0)
 FLAG_HINGE2 = 32                 # hinge angle matches the second Lewis moment too
+FLAG_BHABHA = 64                 # positrons: Bhabha events and positron stopping power
 
 E_ABS_E = 0.2                   # MeV
 E_ABS_G = 0.05                  # MeV
@@ -252,6 +259,52 @@ def l_col(m: Material, t: float, w_cut: float | None, density: bool = False) -> 
     return pref * (math.log(2.0 * (tau + 2.0) / i_mc2 ** 2) + f - delta)
 
 
+def l_col_positron(m: Material, t: float, w_cut: float | None, density: bool = False) -> float:
+    """Bethe collision stopping power of positrons with the Bhabha term
+    (Seltzer and Berger's restricted form), restricted to energy losses below
+    w_cut (None: unrestricted; a positron can lose all of t).  With
+    d = min(w_cut, t) / m c^2, y = 1 / (tau + 2):
+      ln(2 (tau + 2) / (I/mc^2)^2) + ln(tau d)
+        - (beta^2 / tau) [tau + 2d - y (3d^2/2 + y (d - d^3/3 + y (d^2/2 - tau d^3/3 + d^4/4)))]
+    which at d = tau is ln(tau^2 (tau + 2) / (2 (I/mc^2)^2)) + F+(tau) with
+    F+ = 2 ln 2 - (beta^2 / 12) (23 + 14 y + 10 y^2 + 4 y^3)."""
+    tau, _, beta2 = _kin(t)
+    w = t if w_cut is None else min(w_cut, t)
+    d = w / MC2
+    y = 1.0 / (tau + 2.0)
+    i_mc2 = m.i_ev * 1e-6 / MC2
+    poly = tau + 2.0 * d - y * (1.5 * d * d + y * (d - d ** 3 / 3.0
+                                                   + y * (d * d / 2.0 - tau * d ** 3 / 3.0 + d ** 4 / 4.0)))
+    pref = 2.0 * math.pi * R_E ** 2 * MC2 * N_A * m.zoa / beta2
+    delta = density_delta(m, t) if density else 0.0
+    return pref * (math.log(2.0 * (tau + 2.0) / i_mc2 ** 2) + math.log(tau * d) - beta2 / tau * poly - delta)
+
+
+def bhabha_coeffs(t: float):
+    """b1..b4 of the Bhabha cross section for a positron of kinetic energy t:
+    dsigma/dW = (2 pi r_e^2 m c^2 / beta^2) W^-2 [1 - b1 e + b2 e^2 - b3 e^3 + b4 e^4],
+    e = W / t (W the energy given to the electron, 0 < W < t)."""
+    g = 1.0 + t / MC2
+    a = ((g - 1.0) / g) ** 2
+    return (a * (2.0 * (g + 1.0) ** 2 - 1.0) / (g * g - 1.0),
+            a * (3.0 * (g + 1.0) ** 2 + 1.0) / (g + 1.0) ** 2,
+            a * 2.0 * g * (g - 1.0) / (g + 1.0) ** 2,
+            a * (g - 1.0) ** 2 / (g + 1.0) ** 2)
+
+
+def sigma_bhabha_hard(m: Material, t: float, w_cc: float) -> float:
+    """Bhabha cross section per gram for energy transfers above w_cc, in closed
+    form: (1/t) int_{e_c}^1 e^-2 [1 - b1 e + ...] de, e_c = w_cc / t."""
+    if t <= w_cc:
+        return 0.0
+    _, _, beta2 = _kin(t)
+    b1, b2, b3, b4 = bhabha_coeffs(t)
+    ec = w_cc / t
+    br = (1.0 / ec - 1.0) + b1 * math.log(ec) + b2 * (1.0 - ec) - b3 * (1.0 - ec * ec) / 2.0 \
+        + b4 * (1.0 - ec ** 3) / 3.0
+    return N_A * m.zoa * 2.0 * math.pi * R_E ** 2 * MC2 / (beta2 * t) * br
+
+
 def l_rad(m: Material, t: float, w_cut: float | None) -> float:
     """Radiative stopping power of the flat W dsigma/dW model, restricted to W < w_cut."""
     w = t if w_cut is None else min(w_cut, t)
@@ -334,10 +387,9 @@ class Tables:
         return write_blob(self)
 
 
-def _range_table(m: Material, e: np.ndarray, lr) -> np.ndarray:
+def _range_table(m: Material, e: np.ndarray, lr, kinks=(E_ABS_G, 2.0 * E_ABS_E)) -> np.ndarray:
     """R(E_i) = R_0 + int_{E_0}^{E_i} dT / L_r(T), R_0 = E_0 / L_r(E_0), by adaptive
     quadrature over each grid interval (kinks of L_r are passed as break points)."""
-    kinks = (E_ABS_G, 2.0 * E_ABS_E)
     r = np.empty_like(e)
     r[0] = e[0] / lr(e[0])
     for i in range(1, len(e)):
@@ -365,7 +417,11 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
       "rayleigh"  standard, with Rayleigh scattering tabulated;
       "hinge2"    standard tables; the hinge angle matches the second Lewis
                   moment exp(-s/lambda2) as well as the first;
-      "refined"   every refinement above: angular, density, rayleigh, hinge2.
+      "bhabha"    standard tables; positrons take their own stopping power
+                  and range and hard Bhabha events instead of Moller ones;
+      "refined"   every refinement above: angular, density, rayleigh, hinge2,
+                  bhabha.
+    The positron quantities are tabulated for every variant.
     """
     e = energy_grid()
     n_mat = len(materials)
@@ -383,8 +439,10 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
         flags |= FLAG_RAYLEIGH
     elif variant == "hinge2":
         flags |= FLAG_HINGE2
+    elif variant == "bhabha":
+        flags |= FLAG_BHABHA
     elif variant == "refined":
-        flags |= FLAG_ANGULAR | FLAG_DENSITY | FLAG_RAYLEIGH | FLAG_HINGE2
+        flags |= FLAG_ANGULAR | FLAG_DENSITY | FLAG_RAYLEIGH | FLAG_HINGE2 | FLAG_BHABHA
     elif variant != "standard":
         raise ValueError(f"unknown table variant {variant!r}")
     w_cc = None if flags & FLAG_NO_HARD else E_ABS_E
@@ -394,6 +452,9 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
 
         def lr(t, m=m, dens=dens):
             return l_col(m, t, w_cc, dens) + l_rad(m, t, w_cr)
+
+        def lr_pos(t, m=m, dens=dens):
+            return l_col_positron(m, t, w_cc, dens) + l_rad(m, t, w_cr)
         for i, ei in enumerate(e):
             if not flags & FLAG_PE_ONLY:
                 data[mi, Q_MU_C, i] = mu_compton(m, ei)
@@ -407,7 +468,11 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
                 data[mi, Q_SIGMA_M, i] = sigma_moller_hard(m, ei, E_ABS_E)
                 data[mi, Q_SIGMA_B, i] = sigma_brems_hard(m, ei, E_ABS_G)
             data[mi, Q_L_R, i] = lr(ei)
+            data[mi, Q_L_R_POS, i] = lr_pos(ei)
+            if not flags & FLAG_NO_HARD:
+                data[mi, Q_SIGMA_BH, i] = sigma_bhabha_hard(m, ei, E_ABS_E)
         data[mi, Q_RANGE] = _range_table(m, e, lr)
+        data[mi, Q_RANGE_POS] = _range_table(m, e, lr_pos, kinks=(E_ABS_G, E_ABS_E))
     return Tables(energies=e, data=data, materials=tuple(materials),
                   kappa_step=kappa_step, a_hinge=solve_a_hinge(kappa_step), flags=flags)
 

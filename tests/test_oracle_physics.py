@@ -365,6 +365,85 @@ def test_csda_track_length_equals_range_difference():
         assert r["cnt"]["moller"] == 0 and r["cnt"]["brems"] == 0
 
 
+def _blob_with_flags(variant, extra, e_abs_g=None):
+    t = T.build_tables(variant=variant)
+    t.flags |= extra
+    if e_abs_g is not None:
+        t.e_abs_g = e_abs_g
+    return T.write_blob(t)
+
+
+def test_positron_csda_track_length_uses_positron_range():
+    """No hard events, Bhabha flag: a positron's path length is
+    (R+(T0) - R+(E_abs)) / rho on the positron range; without the flag it is
+    the electron range difference.  The photon cutoff is raised above m c^2 so
+    the annihilation photons deposit on the spot and set no electrons moving."""
+    for flags, q in ((T.FLAG_BHABHA, T.Q_RANGE_POS), (0, T.Q_RANGE)):
+        b = _blob_with_flags("no_hard", flags, e_abs_g=0.6)
+        t = T.read_blob(b)
+        ph = phantoms.homogeneous(40, 40, 40, 1.0)
+        x, y = ph.centre_xy()
+        ln_e = np.log(t.energies)
+        rr = t.data[T.MAT_WATER, q]
+        for e0 in (15.0, 2.2):
+            r = oracle.simulate(b, ph, sources.pencil(POSITRON, e0, x + 0.25, y + 0.25), 300, seed=34,
+                                history=True)
+            expected = np.interp(math.log(e0), ln_e, rr) - np.interp(math.log(T.E_ABS_E), ln_e, rr)
+            h = r["hist"]
+            full = np.isclose(h["track_e"], expected, rtol=1e-12)
+            assert full.mean() > 0.9                  # the rest backscatter out of the top face
+            assert np.all(h["track_e"][~full] < expected)
+            assert r["cnt"]["bhabha"] == 0 and r["cnt"]["moller"] == 0
+
+
+def test_bhabha_events_take_the_positron_cross_section():
+    """Bhabha flag, energy-independent cross sections with Sigma_M = 0 and
+    Sigma_B = 0: only positrons have hard events, at Sigma_Bh per g/cm^2 of
+    their path.  A positron whose CSDA path would end inside the phantom is
+    cut short by its first Bhabha event, so over 10 MeV primaries the number
+    of events per history is Sigma_Bh times the mean positron path, which lies
+    between the path to the first event and the CSDA range.  Without the flag
+    positrons take Sigma_M = 0 and have none."""
+    t = T.read_blob(T.standard_blob("bhabha"))
+    s_bh = 0.2
+    t.data[:, T.Q_SIGMA_BH] = s_bh
+    t.data[:, T.Q_SIGMA_B] = 0.0
+    t.data[:, T.Q_SIGMA_M] = 0.0
+    b = T.write_blob(t)
+    ph = phantoms.homogeneous(40, 40, 40, 1.0)
+    x, y = ph.centre_xy()
+    src = sources.pencil(POSITRON, 10.0, x + 0.25, y + 0.25)
+    n = 2000
+    r = oracle.simulate(b, ph, src, n, seed=35)
+    c = r["cnt"]
+    assert c["moller"] == 0 and c["brems"] == 0
+    events = c["bhabha"] + c["void"]
+    csda = np.interp(math.log(10.0), np.log(t.energies), t.data[T.MAT_WATER, T.Q_RANGE_POS])
+    # at least one event per history unless the whole CSDA path has none
+    p_none = math.exp(-s_bh * csda)
+    assert events >= n * (1 - p_none) * 0.95
+    assert events <= s_bh * csda * n * 1.05
+    t.flags = 0
+    r0 = oracle.simulate(T.write_blob(t), ph, src, n, seed=35)
+    assert r0["cnt"]["bhabha"] == 0 and r0["cnt"]["moller"] == 0 and r0["cnt"]["void"] == 0
+
+
+@pytest.mark.parametrize("t", [0.5, 3.0, 15.0])
+def test_bhabha_sampler_follows_its_dcs(t):
+    """Bhabha energy transfer e = W/T on [W_cc/T, 1] against quadrature of
+    e^-2 [1 - b1 e + b2 e^2 - b3 e^3 + b4 e^4] per bin."""
+    blob = T.standard_blob("bhabha")
+    e = oracle.sample(blob, 512, t, 300_000, seed=28)[:, 0]
+    b1, b2, b3, b4 = T.bhabha_coeffs(t)
+    ec = T.E_ABS_E / t
+    pdf = lambda x: (1 - b1 * x + b2 * x * x - b3 * x ** 3 + b4 * x ** 4) / (x * x)
+    edges = np.geomspace(ec, 1.0, 41)
+    pb = np.array([integrate.quad(pdf, a_, b_)[0] for a_, b_ in zip(edges[:-1], edges[1:])])
+    pb /= pb.sum()
+    assert e.min() >= ec and e.max() <= 1.0
+    assert _chi2_pvalue(np.histogram(e, edges)[0], pb) > 1e-3
+
+
 def test_hinge_and_hard_event_rates_along_a_track(blob):
     """With energy-independent transport and hard cross sections the step
     algorithm consumes them exactly, so over all electron paths L (g/cm^2):

@@ -316,3 +316,69 @@ def test_rayleigh_tables_only_in_flagged_blobs():
     np.testing.assert_array_equal(std.data[:, other], ray.data[:, other])
     assert ray.flags == T.FLAG_RAYLEIGH
     assert oracle.blob_check(T.standard_blob("refined")) == 4
+
+
+# ------------------------------------------------------------ positrons (Bhabha)
+
+def _bhabha_dcs(t, w):
+    """Bhabha dsigma/dW per electron, from the coefficients under test."""
+    _, _, beta2 = T._kin(t)
+    b1, b2, b3, b4 = T.bhabha_coeffs(t)
+    e = w / t
+    return 2 * math.pi * T.R_E ** 2 * T.MC2 / beta2 / w ** 2 * (1 - b1 * e + b2 * e * e - b3 * e ** 3 + b4 * e ** 4)
+
+
+@pytest.mark.parametrize("t", [0.25, 0.6, 2.0, 8.0, 20.0])
+def test_positron_restricted_plus_hard_bhabha_equals_unrestricted(t):
+    """Three independent published forms meet: the restricted positron stopping
+    power (Seltzer-Berger) plus the energy lost in Bhabha events above the cut
+    (quadrature of W dsigma/dW) equals the unrestricted one with ICRU 37's F+."""
+    for m in (T.MATERIALS[T.MAT_WATER], T.MATERIALS[T.MAT_BONE]):
+        tau, _, beta2 = T._kin(t)
+        y = 1 / (tau + 2)
+        i_mc2 = m.i_ev * 1e-6 / T.MC2
+        f_plus = 2 * math.log(2) - beta2 / 12 * (23 + 14 * y + 10 * y * y + 4 * y ** 3)
+        pref = 2 * math.pi * T.R_E ** 2 * T.MC2 * T.N_A * m.zoa / beta2
+        unres = pref * (math.log(tau * tau * (tau + 2) / (2 * i_mc2 ** 2)) + f_plus)
+        assert T.l_col_positron(m, t, None) == pytest.approx(unres, rel=1e-12)
+        cut = 0.2
+        # in ln W, where the integrand W^2 dsigma/dW is smooth
+        hard, _ = integrate.quad(lambda lw: math.exp(2 * lw) * _bhabha_dcs(t, math.exp(lw)),
+                                 math.log(cut), math.log(t), epsrel=1e-13, epsabs=0)
+        assert T.l_col_positron(m, t, cut) + T.N_A * m.zoa * hard == pytest.approx(unres, rel=1e-9)
+        # and the hard cross section is the integral of the same DCS
+        n, _ = integrate.quad(lambda lw: math.exp(lw) * _bhabha_dcs(t, math.exp(lw)),
+                              math.log(cut), math.log(t), epsrel=1e-13, epsabs=0)
+        assert T.sigma_bhabha_hard(m, t, cut) == pytest.approx(T.N_A * m.zoa * n, rel=1e-9)
+
+
+def test_bhabha_limits_and_rejection_bound():
+    """Ultra-relativistic limit: the bracket becomes (1 - e + e^2)^2.
+    Non-relativistic limit: the Rutherford 1/W^2 (every b_i -> 0).  The bracket
+    never exceeds 1 on [0, 1], so it serves as an acceptance probability."""
+    b = T.bhabha_coeffs(1e6)
+    for x in np.linspace(0, 1, 11):
+        assert 1 - b[0] * x + b[1] * x * x - b[2] * x ** 3 + b[3] * x ** 4 == pytest.approx(
+            (1 - x + x * x) ** 2, abs=1e-5)
+    assert max(T.bhabha_coeffs(1e-7)) < 1e-5          # b1 = O(tau)
+    x = np.linspace(0, 1, 2001)
+    for t in np.geomspace(0.01, 20, 40):
+        b1, b2, b3, b4 = T.bhabha_coeffs(t)
+        g = 1 - b1 * x + b2 * x * x - b3 * x ** 3 + b4 * x ** 4
+        assert g.max() <= 1 + 1e-15 and g.min() > 0
+
+
+def test_positron_tables():
+    t = T.read_blob(T.standard_blob())
+    for m in range(4):
+        assert np.all(np.diff(t.data[m, T.Q_RANGE_POS]) > 0)
+    w = T.MAT_WATER
+    e = t.energies
+    i = np.searchsorted(e, 0.3)
+    # hard Bhabha events exist above W_cc (a positron may lose all its energy),
+    # hard Moller events only above 2 W_cc
+    assert t.data[w, T.Q_SIGMA_BH, i] > 0 and t.data[w, T.Q_SIGMA_M, i] == 0
+    # electron and positron ranges agree within a few per cent
+    sel = e > 0.3
+    rel = np.abs(t.data[w, T.Q_RANGE_POS, sel] / t.data[w, T.Q_RANGE, sel] - 1)
+    assert rel.max() < 0.05
