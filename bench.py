@@ -237,9 +237,10 @@ def main():
 
     # ------------------------------------------------------------ table variants
     # physics refinements behind table flags: emission angles, the density
-    # effect, Rayleigh scattering, and all three together
+    # effect, Rayleigh scattering, the second-moment hinge, Bhabha events for
+    # positrons, and all of them together
     variants = {}
-    for variant in ("angular", "density", "rayleigh", "refined"):
+    for variant in ("angular", "density", "rayleigh", "hinge2", "bhabha", "refined"):
         thv = eng.load_materials(tables.standard_blob(variant))
         cur = {}
         for w, n in ((wg, 20_000_000), (we, 4_000_000)):

@@ -104,6 +104,7 @@ enum {
     MCD_C_ITERS, MCD_C_LIVE, MCD_C_IT_FETCH, MCD_C_IT_PHOTON, MCD_C_IT_ELECTRON, MCD_C_IT_HARD,
     MCD_C_LN_FETCH, MCD_C_LN_PHOTON, MCD_C_LN_ELECTRON, MCD_C_LN_HARD,
     MCD_C_RAYLEIGH,  /* coherent scatterings (tables with the Rayleigh flag) */
+    MCD_C_BHABHA,    /* hard Bhabha events (tables with the Bhabha flag) */
     MCD_NCOUNT = 40
 };
 
@@ -193,13 +194,14 @@ int mcd_create(int device, uint64_t hbm_budget_bytes, mcd_ctx** out);
 int mcd_destroy(mcd_ctx* ctx);
 
 /* Loads a physics table blob (cross sections per interaction, material and
- * energy, Sec. 2.2; format: magic "MCDTAB\0\1", version 3, 512-node log grid
- * from 1 keV to 20 MeV, 10 quantities per material, at most 8 materials).
+ * energy, Sec. 2.2; format: magic "MCDTAB\0\1", version 4, 512-node log grid
+ * from 1 keV to 20 MeV, 13 quantities per material, at most 8 materials).
  * Header flags select physics refinements beyond the paper's scheme:
  *   4  emission angles (Sauter photoelectrons, forward-peaked bremsstrahlung
  *      photons and pair leptons),  8  density effect (tables only),
  *   16 Rayleigh scattering (mu_R tabulated),
- *   32 hinge angles matching the second Lewis moment (from lambda2);
+ *   32 hinge angles matching the second Lewis moment (from lambda2),
+ *   64 positrons with their own range and hard Bhabha events;
  * 1 and 2 mark test tables.  Other bits are rejected.  The blob is validated
  * (sizes, monotone ranges, non-negative finite values, scalar ranges) and
  * converted to FP32 device tables.  *out_tables receives a handle; the blob

@@ -33,6 +33,9 @@ struct DevTables {
     float ray_b[kMaxMat];   // Rayleigh form-factor scale: b = ray_b[m] E^2 (1/MeV^2)
     const float4* hinge;    // [m*512 + i] = (A, B, S, 0) of the second-moment hinge law
     int hinge2;             // 1: hinge angles from the second-moment law
+    const float2* posi;     // [m*512 + i] = (R+, Sigma_Bh/rho): positron range and hard Bhabha
+    float r_abs_pos[kMaxMat];  // R+(E_abs,e) per material
+    int bhabha;             // 1: positrons take posi and Bhabha events
 };
 
 // Source descriptor as the kernels see it.

@@ -233,7 +233,7 @@ size_t plain_lane_bytes(int stack_depth, int slots)
 
 int transport_lds_bytes(int n_mat)
 {
-    return 2 * n_mat * kNE * (int)sizeof(float4) + (kNE + 2 * kMaxMat + 68 + 64) * (int)sizeof(float);
+    return 2 * n_mat * kNE * (int)sizeof(float4) + (kNE + 3 * kMaxMat + 68 + 64) * (int)sizeof(float);
 }
 
 hipError_t launch_plain(const KPlain& p, int blocks, int threads, bool diag, hipStream_t s)

@@ -40,7 +40,7 @@ constexpr size_t kSmallBytes = (kOffRed + 24 + 63) / 64 * 64;
 static_assert(kOffCnt >= 8 * kBal, "energy balance overlaps the counters");
 static_assert(kSmallBytes % 64 == 0 && kOffRed + 24 <= kSmallBytes, "small block layout");
 
-constexpr int kNQ = 10;           // tabulated quantities per material in a table blob
+constexpr int kNQ = 13;           // tabulated quantities per material in a table blob
 
 struct TableSet {
     DevTables dev{};
@@ -48,9 +48,10 @@ struct TableSet {
     int n_mat = 0;
     double emin = 0, emax = 0, e_abs_e = 0, e_abs_g = 0, w_cc = 0, w_cr = 0;
     double kappa_step = 0, f_e = 0, a_hinge = 0;
-    size_t bytes = 0;                // each of the three device arrays phot, elec, hinge
+    size_t bytes = 0;                // each of phot, elec, hinge (posi: half as many)
     bool live = false;
     const double* range(int m) const { return &q[((size_t)m * kNQ + 3) * kNE]; }
+    const double* range_pos(int m) const { return &q[((size_t)m * kNQ + 10) * kNE]; }
 };
 
 struct PhantomRec {

@@ -156,6 +156,7 @@ int mcd_destroy(mcd_ctx* c)
             c->release(t.dev.phot, t.bytes);
             c->release(t.dev.elec, t.bytes);
             c->release((void*)t.dev.hinge, t.bytes);
+            c->release((void*)t.dev.posi, t.bytes / 2);
         }
     for (auto& p : c->phantoms)
         if (p.live) {
@@ -275,7 +276,7 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
         return c->fail(MCD_E_INVAL, "table blob: bad magic or size");
     const uint32_t ver = rd<uint32_t>(b + 8), n_mat = rd<uint32_t>(b + 12);
     const uint32_t n_e = rd<uint32_t>(b + 16), n_q = rd<uint32_t>(b + 20);
-    if (ver != 3 || n_e != (uint32_t)kNE || n_q != (uint32_t)kNQ)
+    if (ver != 4 || n_e != (uint32_t)kNE || n_q != (uint32_t)kNQ)
         return c->fail(MCD_E_INVAL, "table blob: unsupported version or grid");
     if (n_mat < 1 || n_mat > (uint32_t)kMaxMat)
         return c->fail(MCD_E_INVAL, "table blob: 1 to 8 materials supported");
@@ -294,7 +295,7 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
     ts.f_e = rd<double>(s + 56);
     ts.a_hinge = rd<double>(s + 64);
     const uint32_t flags = rd<uint32_t>(s + 72);
-    if (flags & ~63u) return c->fail(MCD_E_INVAL, "table blob: unknown flags");
+    if (flags & ~127u) return c->fail(MCD_E_INVAL, "table blob: unknown flags");
     if (!(ts.emin > 0 && ts.emax > ts.emin && ts.e_abs_e > ts.emin && ts.e_abs_e < ts.emax &&
           ts.e_abs_g > ts.emin && ts.e_abs_g < ts.emax && ts.w_cc > 0 && ts.w_cr > 0 &&
           ts.kappa_step > 0 && ts.f_e > 0 && ts.f_e < 1 && ts.a_hinge > 0))
@@ -306,15 +307,15 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
     for (double v : ts.q)
         if (!(v >= 0.0) || !std::isfinite(v))
             return c->fail(MCD_E_INVAL, "table blob: negative or non-finite value");
-    for (uint32_t m = 0; m < n_mat; ++m) {
-        const double* r = ts.range(m);
-        for (int i = 1; i < kNE; ++i)
-            if (!(r[i] > r[i - 1])) return c->fail(MCD_E_INVAL, "table blob: range not increasing");
-    }
+    for (uint32_t m = 0; m < n_mat; ++m)
+        for (const double* r : {ts.range(m), ts.range_pos(m)})
+            for (int i = 1; i < kNE; ++i)
+                if (!(r[i] > r[i - 1])) return c->fail(MCD_E_INVAL, "table blob: range not increasing");
     // FP32 device layout: float4 per node for the photon and electron groups
     // and for the second-moment hinge law (left zero unless the blob asks)
     const bool hinge2 = (flags & 32u) != 0;
     std::vector<float4> ph((size_t)n_mat * kNE), el((size_t)n_mat * kNE), hl((size_t)n_mat * kNE);
+    std::vector<float2> po((size_t)n_mat * kNE);
     for (uint32_t m = 0; m < n_mat; ++m)
         for (int i = 0; i < kNE; ++i) {
             const double* q = &ts.q[(size_t)m * kNQ * kNE];
@@ -322,32 +323,37 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
                                           (float)q[2 * kNE + i], (float)q[8 * kNE + i]);
             el[m * kNE + i] = make_float4((float)q[3 * kNE + i], (float)q[4 * kNE + i],
                                           (float)q[5 * kNE + i], (float)q[6 * kNE + i]);
+            po[m * kNE + i] = make_float2((float)q[10 * kNE + i], (float)q[11 * kNE + i]);
             hl[m * kNE + i] = hinge2 && q[4 * kNE + i] > 0.0
                                   ? hinge_law(ts.kappa_step, ts.a_hinge, q[9 * kNE + i] / q[4 * kNE + i])
                                   : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     (void)hipSetDevice(c->device);
     ts.bytes = ph.size() * sizeof(float4);
-    float4* hinge_dev = nullptr;
-    int rc = c->alloc((void**)&ts.dev.phot, ts.bytes, "tables");
-    if (rc) return rc;
-    rc = c->alloc((void**)&ts.dev.elec, ts.bytes, "tables");
-    if (!rc) rc = c->alloc((void**)&hinge_dev, ts.bytes, "tables");
-    if (rc) {
-        c->release(ts.dev.phot, ts.bytes);
-        c->release(ts.dev.elec, ts.bytes);
-        return rc;
+    void* dev[4] = {nullptr, nullptr, nullptr, nullptr};            // phot, elec, hinge, posi
+    const void* host[4] = {ph.data(), el.data(), hl.data(), po.data()};
+    const size_t size[4] = {ts.bytes, ts.bytes, ts.bytes, po.size() * sizeof(float2)};
+    auto release_all = [&] {
+        for (int k = 0; k < 4; ++k) c->release(dev[k], size[k]);
+    };
+    for (int k = 0; k < 4; ++k) {
+        const int rc = c->alloc(&dev[k], size[k], "tables");
+        if (rc) {
+            release_all();
+            return rc;
+        }
     }
-    ts.dev.hinge = hinge_dev;
-    hipError_t e = hipMemcpy(ts.dev.phot, ph.data(), ts.bytes, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ts.dev.elec, el.data(), ts.bytes, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(hinge_dev, hl.data(), ts.bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        c->release(ts.dev.phot, ts.bytes);
-        c->release(ts.dev.elec, ts.bytes);
-        c->release(hinge_dev, ts.bytes);
-        return c->hip_fail(e, "table upload");
+    for (int k = 0; k < 4; ++k) {
+        const hipError_t e = hipMemcpy(dev[k], host[k], size[k], hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            release_all();
+            return c->hip_fail(e, "table upload");
+        }
     }
+    ts.dev.phot = (float4*)dev[0];
+    ts.dev.elec = (float4*)dev[1];
+    ts.dev.hinge = (const float4*)dev[2];
+    ts.dev.posi = (const float2*)dev[3];
     DevTables& d = ts.dev;
     d.n_mat = (int)n_mat;
     for (int m = 0; m < kMaxMat; ++m)
@@ -365,6 +371,10 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
     d.f_e = (float)ts.f_e;
     d.angular = (flags & 4u) ? 1 : 0;
     d.hinge2 = hinge2 ? 1 : 0;
+    d.bhabha = (flags & 64u) ? 1 : 0;
+    for (int m = 0; m < kMaxMat; ++m)
+        d.r_abs_pos[m] =
+            m < (int)n_mat ? (float)host_interp(ts.range_pos(m), ts.e_abs_e, ts.emin, ts.emax) : 0.f;
     // Rayleigh angular law of an exponentially screened atom: screening
     // radius a = 0.885 a0 Z_s^(-1/3), Z_s = B / (Z/A) from the material
     // header (rho, Z/A, I, B, ...); b = 2 (a E / hbar c)^2
@@ -402,6 +412,7 @@ int mcd_unload_materials(mcd_ctx* c, int32_t t)
     c->release(ts.dev.phot, ts.bytes);
     c->release(ts.dev.elec, ts.bytes);
     c->release((void*)ts.dev.hinge, ts.bytes);
+    c->release((void*)ts.dev.posi, ts.bytes / 2);
     ts.live = false;
     ts.q.clear();
     return MCD_OK;

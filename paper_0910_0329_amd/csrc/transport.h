@@ -33,7 +33,7 @@ enum { PHOTON = 0, ELECTRON = 1, POSITRON = 2, DEAD = -1 };
 enum { LIM_E, LIM_H, LIM_K, LIM_B, LIM_F };
 // Event codes of the per-particle hash (diagnostics).
 enum { EV_VIRTUAL = 1, EV_COMPTON, EV_PHOTO, EV_PAIR, EV_PAIR_VOID, EV_G_ESCAPE, EV_G_ABSORB, EV_RAYLEIGH,
-       EV_SEG = 10, EV_MOLLER = 20, EV_BREMS, EV_MOLLER_VOID, EV_E_ESCAPE };
+       EV_SEG = 10, EV_MOLLER = 20, EV_BREMS, EV_MOLLER_VOID, EV_E_ESCAPE, EV_BHABHA, EV_BHABHA_VOID };
 
 DEV float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
@@ -136,6 +136,7 @@ struct Env {
     const float* maj;        // LDS [512]
     const float* r_abs;      // LDS [kMaxMat]
     const float* ray_b;      // LDS [kMaxMat]
+    const float* r_abs_pos;  // LDS [kMaxMat]: R+(E_abs,e) (positron range)
     uint32_t seed, key;      // Philox key of the particle being transported
 };
 
@@ -233,17 +234,40 @@ struct Transport {
 
     DEV void eidx(float e, int& i, float& fr) const { node(epos(e), i, fr); }
 
-    // Inverse of the interpolated range of material m: the node interval holding
-    // r is found by walking down from interval i0 (r does not exceed the range
-    // at the start of the segment), then that linear piece is solved for log E.
-    DEV float range_inverse(int m, float r, int i0) const
+    // A positron under tables with the Bhabha flag takes its own range R+
+    // and hard Bhabha cross section from the global (R+, Sigma_Bh) table, in
+    // place of the electron R and Sigma_M in LDS; everything else is shared.
+    DEV bool own_positron(const Part& q) const { return G().t.bhabha && q.type == POSITRON; }
+
+    // Range node j of material m (electron or positron range).
+    DEV float range_node(int m, int j, bool pos) const
     {
-        const float4* el = env.elec + m * kNE;
+        if (pos) return G().t.posi[m * kNE + j].x;
+        return env.elec[m * kNE + j].x;
+    }
+
+    // Inverse of the interpolated (electron or positron) range of material m.
+    DEV float range_inverse(int m, float r, int i0, bool pos) const
+    {
+        if (pos) return invert_range([&](int j) { return G().t.posi[m * kNE + j].x; }, r, i0);
+        return invert_range([&](int j) { return env.elec[m * kNE + j].x; }, r, i0);
+    }
+
+    // The node interval holding r is found by walking down from interval i0
+    // (r does not exceed the range at the start of the segment), then that
+    // linear piece is solved for log E.
+    template <class F> DEV float invert_range(F rnode, float r, int i0) const
+    {
         int j = i0;
-        while (j > 0 && el[j].x > r) --j;
-        if (el[j].x > r) return G().t.emin;
-        while (j < kNE - 2 && el[j + 1].x <= r) ++j;
-        const float r0 = el[j].x, r1 = el[j + 1].x;
+        float rj = rnode(j);
+        while (j > 0 && rj > r) rj = rnode(--j);
+        if (rj > r) return G().t.emin;
+        float rn = rnode(j + 1);
+        while (j < kNE - 2 && rn <= r) {
+            rj = rn;
+            rn = rnode(++j + 1);
+        }
+        const float r0 = rj, r1 = rn;
         const float fr = fminf(fdiv(r - r0, r1 - r0), 1.0f);
         return exp2f(G().t.l2_emin + ((float)j + fr) * G().t.dl2);
     }
@@ -668,11 +692,18 @@ struct Transport {
         float fr;
         node(xt, i, fr);
         const float4 a = env.elec[m * kNE + i], b = env.elec[m * kNE + i + 1];
-        const float rt = a.x + (b.x - a.x) * fr;
+        float rt = a.x + (b.x - a.x) * fr;
         const float lam = a.y + (b.y - a.y) * fr;
-        const float sh = (a.z + (b.z - a.z) * fr) + (a.w + (b.w - a.w) * fr);
+        float s_inel = a.z + (b.z - a.z) * fr;
+        const bool pos = own_positron(q);
+        if (pos) {
+            const float2 p0 = g.t.posi[m * kNE + i], p1 = g.t.posi[m * kNE + i + 1];
+            rt = p0.x + (p1.x - p0.x) * fr;
+            s_inel = p0.y + (p1.y - p0.y) * fr;
+        }
+        const float sh = s_inel + (a.w + (b.w - a.w) * fr);
         // the five limits, ties resolved in the order E, h, kappa, b, f
-        float l = fmaxf(0.f, (rt - env.r_abs[m]) * irho);
+        float l = fmaxf(0.f, (rt - (pos ? env.r_abs_pos[m] : env.r_abs[m])) * irho);
         int lim = LIM_E;
         const float l_h = sh > 0.f ? fmaxf(0.f, fdiv(q.nh, rho * sh)) : kInf;
         if (l_h < l) { l = l_h; lim = LIM_H; }
@@ -686,7 +717,7 @@ struct Transport {
         int jf;
         float ff;
         node(xt + g.t.f_shift, jf, ff);
-        const float rf0 = env.elec[m * kNE + jf].x, rf1 = env.elec[m * kNE + jf + 1].x;
+        const float rf0 = range_node(m, jf, pos), rf1 = range_node(m, jf + 1, pos);
         const float l_f = (rt - (rf0 + (rf1 - rf0) * ff)) * irho;
         if (l_f < l) { l = l_f; lim = LIM_F; }
         // move and lose energy continuously
@@ -695,7 +726,7 @@ struct Transport {
         q.z += l * q.w;
         float tn;
         if (lim == LIM_E) tn = T > g.t.e_abs_e ? g.t.e_abs_e : T;
-        else tn = fminf(T, range_inverse(m, rt - rho * l, i));
+        else tn = fminf(T, range_inverse(m, rt - rho * l, i, pos));
         const float dep = T - tn;
         e_csda += (double)dep;
         self().deposit(q, vx, dep);
@@ -771,6 +802,55 @@ struct Transport {
     // The hard event that ended the last segment of q (Moller or
     // bremsstrahlung, chosen by their cross sections at T), then the number
     // of mean free paths to the next one.
+    // Bhabha event of a positron of kinetic energy T (T updated): the atomic
+    // electron takes W = e T, e on [w_cc / T, 1] with density
+    // e^-2 [1 - b1 e + b2 e^2 - b3 e^3 + b4 e^4], drawn from e^-2 by inversion
+    // and accepted with the bracket (two uniforms per try).  With tau = T/mc^2
+    // and a = (tau / (tau + 1))^2: b1 = a (2 (tau + 2)^2 - 1) / (tau (tau + 2)),
+    // b2 = a (3 (tau + 2)^2 + 1) / (tau + 2)^2, b3 = 2a (tau + 1) tau / (tau + 2)^2,
+    // b4 = a tau^2 / (tau + 2)^2.  Both leave at the two-body angles.
+    DEV void bhabha(Part& q, float& T, int vx)
+    {
+        const KGeom& g = G();
+        if (T <= g.t.w_cc) {
+            ev(EV_BHABHA_VOID);
+            count(MCD_C_VOID);
+            return;
+        }
+        ev(EV_BHABHA);
+        count(MCD_C_BHABHA);
+        const float e0 = fdiv(g.t.w_cc, T);
+        const float tau = fdiv(T, kMC2);
+        const float r = fdiv(tau, tau + 1.f);
+        const float a = r * r;
+        const float tp = tau + 2.f;
+        const float itp2 = __builtin_amdgcn_rcpf(tp * tp);
+        const float b1 = a * fdiv(2.f * tp * tp - 1.f, tau * tp);
+        const float b2 = a * (3.f * tp * tp + 1.f) * itp2;
+        const float b3 = 2.f * a * (tau + 1.f) * tau * itp2;
+        const float b4 = a * tau * tau * itp2;
+        float eps;
+        for (;;) {
+            eps = fdiv(e0, 1.f - uni(q) * (1.f - e0));
+            const float ua = uni(q);
+            count(MCD_C_MOLLER_TRIES);
+            const float br = 1.f - eps * (b1 - eps * (b2 - eps * (b3 - eps * b4)));
+            if (ua <= br) break;
+        }
+        eps = fminf(eps, 1.f);
+        const float ph = uni(q);
+        const float cp = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
+        const float tn = T - eps * T;          // the positron keeps exactly T - W
+        const float wd = T - tn;
+        const float cs = sqrtf(fdiv(wd * (T + 2.f * kMC2), T * (wd + 2.f * kMC2)));
+        const float cpr = sqrtf(fdiv(tn * (T + 2.f * kMC2), T * (tn + 2.f * kMC2)));
+        float du = q.u, dv = q.v, dw = q.w;
+        rotate(du, dv, dw, fminf(cs, 1.f), -cp, -sph);
+        emit_charged(q, ELECTRON, wd, q.x, q.y, q.z, du, dv, dw, vx);
+        rotate(q.u, q.v, q.w, fminf(cpr, 1.f), cp, sph);
+        T = tn;
+    }
+
     DEV void hard_event(Part& q)
     {
         const KGeom& g = G();
@@ -782,9 +862,17 @@ struct Transport {
         float fr;
         eidx(T, i, fr);
         const float4 a = env.elec[m * kNE + i], b = env.elec[m * kNE + i + 1];
-        const float sm = a.z + (b.z - a.z) * fr;
+        float sm = a.z + (b.z - a.z) * fr;
         const float sb = a.w + (b.w - a.w) * fr;
-        if (uni(q) * (sm + sb) < sm) {
+        const bool pos = own_positron(q);
+        if (pos) {
+            const float2 p0 = g.t.posi[m * kNE + i], p1 = g.t.posi[m * kNE + i + 1];
+            sm = p0.y + (p1.y - p0.y) * fr;
+        }
+        const bool inelastic = uni(q) * (sm + sb) < sm;
+        if (pos && inelastic) {
+            bhabha(q, T, vx);
+        } else if (inelastic) {
             if (T <= 2.f * g.t.w_cc) {
                 ev(EV_MOLLER_VOID);
                 count(MCD_C_VOID);
@@ -923,7 +1011,7 @@ struct Transport {
 };
 
 // Stages the material tables and the majorant into LDS (dynamic shared memory
-// laid out as phot | elec | maj | r_abs | ray_b | extra floats).
+// laid out as phot | elec | maj | r_abs | ray_b | r_abs_pos | extra floats).
 DEV void stage_tables(const KGeom& g, float4* lds, Env& env, float** extra)
 {
     const int nt = g.t.n_mat * kNE;
@@ -932,6 +1020,7 @@ DEV void stage_tables(const KGeom& g, float4* lds, Env& env, float** extra)
     float* s_maj = (float*)(lds + 2 * nt);
     float* s_rabs = s_maj + kNE;
     float* s_rayb = s_rabs + kMaxMat;
+    float* s_rabp = s_rayb + kMaxMat;
     for (int i = threadIdx.x; i < nt; i += blockDim.x) {
         s_phot[i] = g.t.phot[i];
         s_elec[i] = g.t.elec[i];
@@ -940,13 +1029,15 @@ DEV void stage_tables(const KGeom& g, float4* lds, Env& env, float** extra)
     for (int i = threadIdx.x; i < kMaxMat; i += blockDim.x) {
         s_rabs[i] = g.t.r_abs[i];
         s_rayb[i] = g.t.ray_b[i];
+        s_rabp[i] = g.t.r_abs_pos[i];
     }
     env.phot = s_phot;
     env.elec = s_elec;
     env.maj = s_maj;
     env.r_abs = s_rabs;
     env.ray_b = s_rayb;
-    *extra = s_rayb + kMaxMat;
+    env.r_abs_pos = s_rabp;
+    *extra = s_rabp + kMaxMat;
 }
 
 }  // namespace mcd

@@ -22,7 +22,7 @@ COUNT_NAMES = ("histories", "flights", "virtual", "compton", "photo", "pair", "s
                "spawns", "philox", "flushes", "escapes", "misses", "local", "void",
                "compton_tries", "moller_tries", "max_stack", "iters", "live", "it_fetch", "it_photon",
                "it_electron", "it_hard", "ln_fetch", "ln_photon", "ln_electron", "ln_hard",
-               "rayleigh")
+               "rayleigh", "bhabha")
 
 
 class McdError(RuntimeError):
