@@ -237,13 +237,21 @@ def test_rayleigh_tables_match_oracle(eng, variant, particle, e, n, kernel):
 @pytest.mark.parametrize("kernel", ("plain", "regrouped"))
 @pytest.mark.parametrize("variant,particle,e,n", [("hinge2", ELECTRON, 12.0, 4_000),
                                                   ("hinge2", PHOTON, 8.0, 30_000),
-                                                  ("refined", ELECTRON, 18.0, 3_000)])
+                                                  ("refined", ELECTRON, 18.0, 3_000),
+                                                  ("hinge2 r=1.8", ELECTRON, 12.0, 4_000)])
 def test_second_moment_hinge_tables_match_oracle(eng, variant, particle, e, n, kernel):
     """Tables with the hinge2 flag: hinge angles from the law matching both
     Lewis moments (the device interpolates its per-node parameters, the
-    oracle solves for them at the hinge energy)."""
+    oracle solves for them at the hinge energy).  "r=1.8" sets
+    lambda1/lambda2 = 1.8 by hand, which takes the law's other branch
+    (undeflected hinges mixed with a wider Wentzel angle)."""
     from paper_0910_0329_amd.inputs import tables
-    blob = tables.standard_blob(variant)
+    if variant == "hinge2 r=1.8":
+        t = tables.read_blob(tables.standard_blob("hinge2"))
+        t.data[:, tables.Q_LAMBDA2_INV] = 1.8 * t.data[:, tables.Q_LAMBDA1_INV]
+        blob = tables.write_blob(t)
+    else:
+        blob = tables.standard_blob(variant)
     thh = eng.load_materials(blob)
     ph = phantoms.random_field_phantom(40, 0.25, seed=56, nz=48)
     x, y = ph.centre_xy()

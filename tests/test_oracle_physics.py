@@ -326,6 +326,36 @@ def test_second_moment_hinge_reproduces_both_lewis_moments(m, e):
     assert abs(q2.mean() - math.exp(-k * r)) > 10 * se(q2)
 
 
+@pytest.mark.parametrize("ratio", [1.2, 1.8, 2.4])
+def test_second_moment_hinge_heavier_tail_branch(ratio):
+    """lambda1/lambda2 set by hand so that the target <mu^2>/<mu> lies above
+    the first-moment Wentzel law's (small ratios): the law then mixes
+    undeflected hinges with a wider Wentzel angle.  Both Lewis moments still
+    hold; some hinges do not deflect at all."""
+    t = T.read_blob(T.standard_blob("hinge2"))
+    t.data[:, T.Q_LAMBDA2_INV] = ratio * t.data[:, T.Q_LAMBDA1_INV]
+    blob = T.write_blob(t)
+    n = 400_000
+    out = oracle.sample(blob, 256 + T.MAT_WATER, 2.0, n, seed=29)
+    c, r = out[:, 0], out[0, 1]
+    assert r == pytest.approx(ratio, rel=1e-12)
+    k = T.KAPPA_STEP
+    p1, p2 = c, 1.5 * c * c - 0.5
+    se = lambda x: x.std() / math.sqrt(n)
+    assert abs(p1.mean() - math.exp(-k)) <= 5 * se(p1)
+    assert abs(p2.mean() - math.exp(-k * r)) <= 5 * se(p2)
+    straight = np.mean(c == 1.0)
+    m1 = 0.5 * (1 - math.exp(-k))
+    m2 = m1 - (1 - math.exp(-k * r)) / 6
+    a1 = t.a_hinge
+    l1 = math.log1p(1 / a1)
+    q1 = (a1 * ((1 + 2 * a1) - 2 * a1 * (1 + a1) * l1)) / (a1 * ((1 + a1) * l1 - 1))
+    if m2 / m1 >= q1:
+        assert straight > 0.01
+    else:
+        assert straight < 1e-4
+
+
 def test_second_moment_hinge_flag_keeps_energy_and_draws(blob):
     """Same histories with and without the hinge2 flag: the source draws and
     the energy balance hold, the dose changes."""
