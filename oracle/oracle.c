@@ -108,6 +108,7 @@ static int load_tables(const void* blob, size_t nbytes, tables* t)
     t->e_abs_g = rd_f64(p + 24); t->w_cc = rd_f64(p + 32); t->w_cr = rd_f64(p + 40);
     t->kappa_step = rd_f64(p + 48); t->f_e = rd_f64(p + 56); t->a_hinge = rd_f64(p + 64);
     t->flags = rd_u32(p + 72);
+    if (t->flags & ~127u) return -1;   /* flags 1, 2, 4, 8, 16, 32, 64 only */
     if (!(t->emin > 0 && t->emax > t->emin && t->e_abs_e > t->emin && t->e_abs_e < t->emax &&
           t->e_abs_g > t->emin && t->e_abs_g < t->emax && t->w_cc > 0 && t->w_cr > 0 &&
           t->kappa_step > 0 && t->f_e > 0 && t->f_e < 1 && t->a_hinge > 0))

@@ -439,4 +439,21 @@ def test_invalid_arguments(eng, blob, th):
         eng.load_phantom(bad, th)
     with pytest.raises(McdError):
         eng.load_materials(blob[:-8])
+    # the blob format and flags the library knows, and nothing else
+    from paper_0910_0329_amd.inputs import tables
+    t = tables.read_blob(blob)
+    t.flags = 128
+    with pytest.raises(McdError) as ei:
+        eng.load_materials(tables.write_blob(t))
+    assert ei.value.status == E_INVAL
+    old = bytearray(blob)
+    old[8:12] = (tables.BLOB_VERSION - 1).to_bytes(4, "little")
+    with pytest.raises(McdError) as ei:
+        eng.load_materials(bytes(old))
+    assert ei.value.status == E_INVAL
+    t = tables.read_blob(blob)
+    t.data[1, tables.Q_RANGE_POS, 7] = t.data[1, tables.Q_RANGE_POS, 6]
+    with pytest.raises(McdError) as ei:
+        eng.load_materials(tables.write_blob(t))
+    assert ei.value.status == E_INVAL
     eng.unload_phantom(pid)

@@ -187,6 +187,16 @@ def test_blob_roundtrip_and_validation(blob):
     t3 = T.read_blob(blob)
     t3.data[1, T.Q_MU_C, 5] = -1.0
     assert oracle.blob_check(T.write_blob(t3)) == -1
+    # the positron range is checked too, and an older format is refused
+    t4 = T.read_blob(blob)
+    t4.data[3, T.Q_RANGE_POS, 100] = t4.data[3, T.Q_RANGE_POS, 99]
+    assert oracle.blob_check(T.write_blob(t4)) == -1
+    old = bytearray(blob)
+    old[8:12] = (T.BLOB_VERSION - 1).to_bytes(4, "little")
+    assert oracle.blob_check(bytes(old)) == -1
+    t5 = T.read_blob(blob)
+    t5.flags = 128
+    assert oracle.blob_check(T.write_blob(t5)) == -1
 
 
 def test_oracle_interpolation_matches_nodes_and_is_linear_in_log_e(blob, tabs):
