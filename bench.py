@@ -179,7 +179,7 @@ def main():
     }
 
     path = PATH_LANE_OPS.get(wg.name)
-    roofline = {"bound": "alu", "kernel": "k_phase<false,true> (photon phase)", "achieved": None,
+    roofline = {"bound": "alu", "kernel": "k_phase<false,true,false> (photon phase)", "achieved": None,
                 "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s", "frac": None, "traffic": None,
                 "per_launch_ms": k_ms / max(launches, 1), "histories_per_launch": n1 / max(launches, 1)}
     if path:

@@ -24,8 +24,11 @@ HIPCC_FLAGS = [
 
 
 # Production (non-diagnostic) transport kernels: checked for private scratch.
-HOT_KERNELS = ("_ZN3mcd7k_plainILb0EEEvNS_6KPlainE", "_ZN3mcd7k_phaseILb0ELb1EEEvNS_6KPhaseE",
-               "_ZN3mcd7k_phaseILb0ELb0EEEvNS_6KPhaseE")
+# the production (no-diagnostics) transport kernels, with and without the
+# refinement code: k_plain<false, REF>, k_phase<false, PHOTONS, REF>
+HOT_KERNELS = ("_ZN3mcd7k_plainILb0ELb0EEEvNS_6KPlainE", "_ZN3mcd7k_plainILb0ELb1EEEvNS_6KPlainE",
+               "_ZN3mcd7k_phaseILb0ELb0ELb0EEEvNS_6KPhaseE", "_ZN3mcd7k_phaseILb0ELb0ELb1EEEvNS_6KPhaseE",
+               "_ZN3mcd7k_phaseILb0ELb1ELb0EEEvNS_6KPhaseE", "_ZN3mcd7k_phaseILb0ELb1ELb1EEEvNS_6KPhaseE")
 
 
 def resource_usage(asm: str) -> dict:

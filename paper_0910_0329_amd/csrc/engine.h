@@ -36,6 +36,8 @@ struct DevTables {
     const float2* posi;     // [m*512 + i] = (R+, Sigma_Bh/rho): positron range and hard Bhabha
     float r_abs_pos[kMaxMat];  // R+(E_abs,e) per material
     int bhabha;             // 1: positrons take posi and Bhabha events
+    int refined;            // any of angular, hinge2, bhabha or mu_R > 0: the kernels
+                            // built with the refinement code must run
 };
 
 // Source descriptor as the kernels see it.
@@ -137,6 +139,7 @@ size_t phase_lane_bytes(int stack_depth);
 int transport_lds_bytes(int n_mat);
 
 // Launchers.
+// Both launchers pick the kernel built for the tables' refinements (p.g.t.refined).
 hipError_t launch_plain(const KPlain& p, int blocks, int threads, bool diag, hipStream_t s);
 hipError_t launch_phase(const KPhase& p, bool photons, int blocks, int threads, bool diag,
                         hipStream_t s);

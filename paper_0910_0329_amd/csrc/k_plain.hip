@@ -14,9 +14,9 @@
 
 namespace mcd {
 
-template <bool DIAG>
-struct PlainLane : Transport<PlainLane<DIAG>, DIAG> {
-    using Base = Transport<PlainLane<DIAG>, DIAG>;
+template <bool DIAG, bool REF>
+struct PlainLane : Transport<PlainLane<DIAG, REF>, DIAG, REF> {
+    using Base = Transport<PlainLane<DIAG, REF>, DIAG, REF>;
     const KPlain& p;
     char* stack;
     uint32_t* keys;
@@ -194,7 +194,7 @@ struct PlainLane : Transport<PlainLane<DIAG>, DIAG> {
     }
 };
 
-template <bool DIAG>
+template <bool DIAG, bool REF>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_plain(KPlain p)
 {
     extern __shared__ float4 lds[];
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     env.key = p.key;
 
     const size_t lane_id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    PlainLane<DIAG> L(p, p.scratch + lane_id * p.lane_bytes);
+    PlainLane<DIAG, REF> L(p, p.scratch + lane_id * p.lane_bytes);
     L.env = env;
     L.init_base();
     L.s_edges = s_edges;
@@ -239,19 +239,23 @@ int transport_lds_bytes(int n_mat)
 hipError_t launch_plain(const KPlain& p, int blocks, int threads, bool diag, hipStream_t s)
 {
     const size_t lds = transport_lds_bytes(p.g.t.n_mat);
-    if (diag) hipLaunchKernelGGL(k_plain<true>, dim3(blocks), dim3(threads), lds, s, p);
-    else hipLaunchKernelGGL(k_plain<false>, dim3(blocks), dim3(threads), lds, s, p);
+    const bool ref = p.g.t.refined != 0;
+    if (diag && ref) hipLaunchKernelGGL((k_plain<true, true>), dim3(blocks), dim3(threads), lds, s, p);
+    else if (diag) hipLaunchKernelGGL((k_plain<true, false>), dim3(blocks), dim3(threads), lds, s, p);
+    else if (ref) hipLaunchKernelGGL((k_plain<false, true>), dim3(blocks), dim3(threads), lds, s, p);
+    else hipLaunchKernelGGL((k_plain<false, false>), dim3(blocks), dim3(threads), lds, s, p);
     return hipGetLastError();
 }
 
 hipError_t init_plain_kernels(int max_lds)
 {
-    hipError_t e = hipFuncSetAttribute((const void*)k_plain<true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_plain<false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    return e;
+    const void* fns[4] = {(const void*)k_plain<true, true>, (const void*)k_plain<true, false>,
+                          (const void*)k_plain<false, true>, (const void*)k_plain<false, false>};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace mcd

@@ -26,8 +26,8 @@
 
 namespace mcd {
 
-template <bool DIAG, bool PHOTONS>
-struct PhaseLane : Transport<PhaseLane<DIAG, PHOTONS>, DIAG> {
+template <bool DIAG, bool PHOTONS, bool REF>
+struct PhaseLane : Transport<PhaseLane<DIAG, PHOTONS, REF>, DIAG, REF> {
     const KPhase& p;
     char* stack;
     int sp;
@@ -44,7 +44,7 @@ struct PhaseLane : Transport<PhaseLane<DIAG, PHOTONS>, DIAG> {
     unsigned int n_in;
     bool more_new;
 
-    DEV PhaseLane(const KPhase& pp, char* base) : Transport<PhaseLane<DIAG, PHOTONS>, DIAG>(pp.g),
+    DEV PhaseLane(const KPhase& pp, char* base) : Transport<PhaseLane<DIAG, PHOTONS, REF>, DIAG, REF>(pp.g),
                                                    p(pp), stack(base), sp(0), cur_v(-1), cur_e(0.f),
                                                    slot(-1), tally(nullptr), hist(nullptr), first(0),
                                                    p_edep(0.0), p_track(0.0) {}
@@ -205,7 +205,7 @@ struct PhaseLane : Transport<PhaseLane<DIAG, PHOTONS>, DIAG> {
     }
 };
 
-template <bool DIAG, bool PHOTONS>
+template <bool DIAG, bool PHOTONS, bool REF>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_phase(KPhase p)
 {
     extern __shared__ float4 lds[];
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     __syncthreads();
 
     const size_t lane_id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    PhaseLane<DIAG, PHOTONS> L(p, p.scratch + lane_id * p.lane_bytes);
+    PhaseLane<DIAG, PHOTONS, REF> L(p, p.scratch + lane_id * p.lane_bytes);
     L.env = env;
     L.init_base();
     L.n_in = min(p.q_in_ctl->count, p.q_cap);
@@ -237,26 +237,35 @@ size_t phase_lane_bytes(int stack_depth)
     return (b + 255) & ~(size_t)255;
 }
 
+// The instance for (diagnostics, photon phase, refinements) = bits 4, 2, 1 of which.
+static void (*phase_kernel(int which))(KPhase)
+{
+    switch (which) {
+    case 0: return k_phase<false, false, false>;
+    case 1: return k_phase<false, false, true>;
+    case 2: return k_phase<false, true, false>;
+    case 3: return k_phase<false, true, true>;
+    case 4: return k_phase<true, false, false>;
+    case 5: return k_phase<true, false, true>;
+    case 6: return k_phase<true, true, false>;
+    default: return k_phase<true, true, true>;
+    }
+}
+
 hipError_t launch_phase(const KPhase& p, bool photons, int blocks, int threads, bool diag,
                         hipStream_t s)
 {
     const size_t lds = transport_lds_bytes(p.g.t.n_mat);
-    if (photons) {
-        if (diag) hipLaunchKernelGGL((k_phase<true, true>), dim3(blocks), dim3(threads), lds, s, p);
-        else hipLaunchKernelGGL((k_phase<false, true>), dim3(blocks), dim3(threads), lds, s, p);
-    } else {
-        if (diag) hipLaunchKernelGGL((k_phase<true, false>), dim3(blocks), dim3(threads), lds, s, p);
-        else hipLaunchKernelGGL((k_phase<false, false>), dim3(blocks), dim3(threads), lds, s, p);
-    }
+    const int which = (diag ? 4 : 0) | (photons ? 2 : 0) | (p.g.t.refined ? 1 : 0);
+    hipLaunchKernelGGL(phase_kernel(which), dim3(blocks), dim3(threads), lds, s, p);
     return hipGetLastError();
 }
 
 hipError_t init_phase_kernels(int max_lds)
 {
-    const void* fns[4] = {(const void*)k_phase<true, true>, (const void*)k_phase<false, true>,
-                          (const void*)k_phase<true, false>, (const void*)k_phase<false, false>};
-    for (const void* f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    for (int which = 0; which < 8; ++which) {
+        const hipError_t e = hipFuncSetAttribute((const void*)phase_kernel(which),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

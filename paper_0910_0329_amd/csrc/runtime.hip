@@ -372,6 +372,9 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
     d.angular = (flags & 4u) ? 1 : 0;
     d.hinge2 = hinge2 ? 1 : 0;
     d.bhabha = (flags & 64u) ? 1 : 0;
+    bool any_mu_r = false;
+    for (const float4& v : ph) any_mu_r = any_mu_r || v.w > 0.f;
+    d.refined = (d.angular || d.hinge2 || d.bhabha || any_mu_r) ? 1 : 0;
     for (int m = 0; m < kMaxMat; ++m)
         d.r_abs_pos[m] =
             m < (int)n_mat ? (float)host_interp(ts.range_pos(m), ts.e_abs_e, ts.emin, ts.emax) : 0.f;

@@ -140,7 +140,11 @@ struct Env {
     uint32_t seed, key;      // Philox key of the particle being transported
 };
 
-template <class D, bool DIAG>
+// REF: compiled with the physics refinements that tables may switch on
+// (emission angles, Rayleigh scattering, the second-moment hinge, Bhabha
+// events).  Tables that use none of them run the kernels built without that
+// code, which keeps the transport loop smaller.
+template <class D, bool DIAG, bool REF>
 struct Transport {
     // Bound to the kernel argument itself, so that geometry and table scalars
     // stay wave-uniform scalar loads.
@@ -237,7 +241,7 @@ struct Transport {
     // A positron under tables with the Bhabha flag takes its own range R+
     // and hard Bhabha cross section from the global (R+, Sigma_Bh) table, in
     // place of the electron R and Sigma_M in LDS; everything else is shared.
-    DEV bool own_positron(const Part& q) const { return G().t.bhabha && q.type == POSITRON; }
+    DEV bool own_positron(const Part& q) const { return REF && G().t.bhabha && q.type == POSITRON; }
 
     // Range node j of material m (electron or positron range).
     DEV float range_node(int m, int j, bool pos) const
@@ -553,7 +557,7 @@ struct Transport {
         const float mu_c = rho * (a.x + (b.x - a.x) * fr);
         const float mu_pe = rho * (a.y + (b.y - a.y) * fr);
         const float mu_pp = rho * (a.z + (b.z - a.z) * fr);
-        const float mu_r = rho * (a.w + (b.w - a.w) * fr);
+        const float mu_r = REF ? rho * (a.w + (b.w - a.w) * fr) : 0.f;
         const float xs = uni(q) * mu_max;
         if (xs < mu_c) {
             ev(EV_COMPTON);
@@ -565,7 +569,7 @@ struct Transport {
             // the photoelectron leaves along the photon, or (angular tables,
             // if it is transported) at a Sauter angle to it
             float du = q.u, dv = q.v, dw = q.w;
-            if (G().t.angular && q.e > G().t.e_abs_e) {
+            if (REF && G().t.angular && q.e > G().t.e_abs_e) {
                 const float cost = sauter_cos(q, q.e);
                 const float ph = uni(q);
                 rotate(du, dv, dw, cost, __builtin_amdgcn_cosf(ph), __builtin_amdgcn_sinf(ph));
@@ -582,7 +586,7 @@ struct Transport {
                 // both leptons along the photon, or (angular tables, each one
                 // that is transported) at a forward angle to it
                 float du = q.u, dv = q.v, dw = q.w;
-                if (G().t.angular && tm > G().t.e_abs_e) {
+                if (REF && G().t.angular && tm > G().t.e_abs_e) {
                     const float cost = forward_cos(q, tm);
                     const float ph = uni(q);
                     rotate(du, dv, dw, cost, __builtin_amdgcn_cosf(ph), __builtin_amdgcn_sinf(ph));
@@ -591,7 +595,7 @@ struct Transport {
                 du = q.u;
                 dv = q.v;
                 dw = q.w;
-                if (G().t.angular && tp > G().t.e_abs_e) {
+                if (REF && G().t.angular && tp > G().t.e_abs_e) {
                     const float cost = forward_cos(q, tp);
                     const float ph = uni(q);
                     rotate(du, dv, dw, cost, __builtin_amdgcn_cosf(ph), __builtin_amdgcn_sinf(ph));
@@ -602,7 +606,7 @@ struct Transport {
                 ev(EV_PAIR_VOID);
                 count(MCD_C_VOID);
             }
-        } else if (xs < mu_c + mu_pe + mu_pp + mu_r) {
+        } else if (REF && xs < mu_c + mu_pe + mu_pp + mu_r) {
             // coherent: same energy, new direction
             ev(EV_RAYLEIGH);
             count(MCD_C_RAYLEIGH);
@@ -750,7 +754,7 @@ struct Transport {
                 count(MCD_C_HINGES);
                 const float u = uni(q);
                 float mu;
-                if (g.t.hinge2) {
+                if (REF && g.t.hinge2) {
                     // second-moment law at the energy the hinge is reached
                     // with: no deflection when u >= B, else a Wentzel angle
                     // of screening A compressed by S
@@ -912,7 +916,7 @@ struct Transport {
             // forward angle to it; the azimuth is drawn either way
             const float ph = uni(q);
             float du = q.u, dv = q.v, dw = q.w;
-            if (g.t.angular) {
+            if (REF && g.t.angular) {
                 const float cost = forward_cos(q, T);
                 rotate(du, dv, dw, cost, __builtin_amdgcn_cosf(ph), __builtin_amdgcn_sinf(ph));
             }
