@@ -162,7 +162,9 @@ typedef struct {
     int32_t sched_fetch_div;
     int32_t sched_hard_div;
     int32_t sched_photon_div;
-    int32_t reserved0;
+    int32_t refined_build;    /* 1: run the transport kernels built with the refinement code
+                                 even when the tables use none of it (the same histories;
+                                 a check of the lean build).  0 = pick by the tables */
 } mcd_opts;
 
 /* Output of a run.  dose and sigma (nx*ny*nz doubles each, Gy per source

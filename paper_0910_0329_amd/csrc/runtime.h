@@ -106,6 +106,7 @@ struct RegroupPlan {
     int depth = 0;
     int fp32 = 0;
     bool diag = false;
+    bool refined_build = false;      // force the kernels built with the refinement code
     bool use_queues = false;
     Sched sched{};
     std::vector<ReqDev> req;

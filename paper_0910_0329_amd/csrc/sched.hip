@@ -111,9 +111,12 @@ int mcd_ctx::simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n_h
     if (want_final && (!out->on_device || !out->dose || !out->sigma))
         if ((rc = ensure_stage(ph.nv, s))) return rc;
 
+    if (opts && (opts->refined_build < 0 || opts->refined_build > 1))
+        return fail(MCD_E_INVAL, "opts: refined_build must be 0 or 1");
     KPlain p;
     std::memset(&p, 0, sizeof p);
     fill_geom(p.g, ph);
+    if (opts && opts->refined_build) p.g.t.refined = 1;
     p.src = ds;
     p.seed = (uint32_t)seed;
     p.key = request_key;
@@ -241,6 +244,9 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
     plan.use_queues = opts && opts->regroup == 1;
     plan.fp32 = opts && opts->tally_fp32 ? 1 : 0;
     plan.diag = opts && opts->diagnostics;
+    if (opts && (opts->refined_build < 0 || opts->refined_build > 1))
+        return fail(MCD_E_INVAL, "opts: refined_build must be 0 or 1");
+    plan.refined_build = opts && opts->refined_build;
     if (opts && opts->history_records && (!plan.diag || n_req != 1))
         return fail(MCD_E_INVAL, "history records need diagnostics and a single request");
     int rc = launch_shape(opts, tables[ph.tables].n_mat, &plan.blocks, &plan.threads);
@@ -356,6 +362,7 @@ int mcd_ctx::enqueue_cycles(const RegroupPlan& plan, int c0, int c1, hipStream_t
     KPhase k;
     std::memset(&k, 0, sizeof k);
     fill_geom(k.g, ph);
+    if (plan.refined_build) k.g.t.refined = 1;
     k.req = rb.req;
     k.n_req = plan.n_req;
     k.tally_fp32 = plan.fp32;
@@ -550,6 +557,7 @@ int mcd::run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_g
         add(&plan.depth, sizeof plan.depth);
         add(&plan.fp32, sizeof plan.fp32);
         add(&plan.diag, sizeof plan.diag);
+        add(&plan.refined_build, sizeof plan.refined_build);
         add(&plan.use_queues, sizeof plan.use_queues);
         add(&plan.sched, sizeof plan.sched);
         add(&clear_tally, sizeof clear_tally);
