@@ -203,6 +203,20 @@ struct Transport {
     DEV float uni(Part& q)
     {
         if ((q.d >> 2) >= q.g) refill(q);
+        return uni_ready(q);
+    }
+
+    // At least n <= 4 undrawn words in the ring.  With fewer left the lane
+    // draws from its newest block, so the older slot is spent and one refill
+    // suffices.  Rejection loops call it once per try and then draw with
+    // uni_ready, one ring check where each draw would make its own.
+    DEV void ensure(Part& q, uint32_t n)
+    {
+        if (4u * q.g - q.d < n) refill(q);
+    }
+
+    DEV float uni_ready(Part& q)
+    {
         const uint32_t k = q.d & 3u;
         uint32_t x;
         if ((q.d >> 2) & 1u) x = k == 0 ? q.r4 : (k == 1 ? q.r5 : (k == 2 ? q.r6 : q.r7));
@@ -450,9 +464,9 @@ struct Transport {
         if (DIAG) p_hash = (0xcbf29ce484222325ull ^ ((uint64_t)q.l1 << 32 | q.l0)) * 0x100000001b3ull;
         if (q.type != PHOTON) {
             floor_voxel(q.x, q.y, q.z, q.ix, q.iy, q.iz);
-            prefetch(q);
-            q.nh = neg_ln(uni(q));
-            q.xi = uni(q);
+            prefetch(q);                       // leaves >= 2 words
+            q.nh = neg_ln(uni_ready(q));
+            q.xi = uni_ready(q);
             q.kap = q.xi * G().t.kappa_step;
             q.before = 1;
         }
@@ -476,7 +490,8 @@ struct Transport {
         q.g = 0;
         q.nsp = 0;
         q.pend = 0;
-        const float u0 = uni(q), u1 = uni(q), u2 = uni(q), u3 = uni(q);
+        ensure(q, 4);                          // block 0
+        const float u0 = uni_ready(q), u1 = uni_ready(q), u2 = uni_ready(q), u3 = uni_ready(q);
         float e;
         if (s.energy_kind == MCD_MONO) {
             e = s.e0;
@@ -534,7 +549,7 @@ struct Transport {
         float fr;
         eidx(q.e, i, fr);
         const float mu_max = env.maj[i] + (env.maj[i + 1] - env.maj[i]) * fr;
-        const float s = fdiv(neg_ln(uni(q)), mu_max);
+        const float s = fdiv(neg_ln(uni_ready(q)), mu_max);   // prefetch left >= 2 words
         count(MCD_C_FLIGHTS);
         q.x += s * q.u;
         q.y += s * q.v;
@@ -558,7 +573,7 @@ struct Transport {
         const float mu_pe = rho * (a.y + (b.y - a.y) * fr);
         const float mu_pp = rho * (a.z + (b.z - a.z) * fr);
         const float mu_r = REF ? rho * (a.w + (b.w - a.w) * fr) : 0.f;
-        const float xs = uni(q) * mu_max;
+        const float xs = uni_ready(q) * mu_max;
         if (xs < mu_c) {
             ev(EV_COMPTON);
             count(MCD_C_COMPTON);
@@ -630,7 +645,8 @@ struct Transport {
         const float l2tmin = __log2f(tmin);
         float tau, cost;
         for (;;) {
-            const float ua = uni(q), ub = uni(q), uc = uni(q);
+            ensure(q, 4);                      // three for the try, one for the azimuth
+            const float ua = uni_ready(q), ub = uni_ready(q), uc = uni_ready(q);
             count(MCD_C_COMPTON_TRIES);
             if (ua * (a1 + a2) < a1) tau = exp2f(ub * l2tmin);
             else tau = sqrtf(tmin * tmin + ub * (1.f - tmin * tmin));
@@ -638,7 +654,7 @@ struct Transport {
             const float sin2 = 1.f - cost * cost;
             if (uc <= 1.f - fdiv(tau * sin2, 1.f + tau * tau)) break;
         }
-        const float ph = uni(q);
+        const float ph = uni_ready(q);
         const float cp = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
         const float te = e - tau * e;          // electron energy; the photon keeps
         const float e1 = e - te;               // exactly the rest (e1 + te == e)
@@ -752,7 +768,7 @@ struct Transport {
         } else if (lim == LIM_K) {
             if (q.before) {
                 count(MCD_C_HINGES);
-                const float u = uni(q);
+                const float u = uni_ready(q);      // prefetch left >= 2 words
                 float mu;
                 if (REF && g.t.hinge2) {
                     // second-moment law at the energy the hinge is reached
@@ -771,13 +787,13 @@ struct Transport {
                     const float A = g.t.a_hinge;
                     mu = fdiv(A * u, 1.f + A - u);
                 }
-                const float ph = uni(q);
+                const float ph = uni_ready(q);
                 rotate(q.u, q.v, q.w, 1.f - 2.f * mu, __builtin_amdgcn_cosf(ph),
                        __builtin_amdgcn_sinf(ph));
                 q.kap = (1.f - q.xi) * g.t.kappa_step;
                 q.before = 0;
             } else {
-                q.xi = uni(q);
+                q.xi = uni_ready(q);
                 q.kap = q.xi * g.t.kappa_step;
                 q.before = 1;
             }
@@ -889,14 +905,15 @@ struct Transport {
                 const float c = fdiv(2.f * tau + 1.f, (tau + 1.f) * (tau + 1.f));
                 float eps;
                 for (;;) {
-                    eps = fdiv(e0, 1.f - uni(q) * (1.f - 2.f * e0));
-                    const float ua = uni(q);
+                    ensure(q, 3);              // two for the try, one for the azimuth
+                    eps = fdiv(e0, 1.f - uni_ready(q) * (1.f - 2.f * e0));
+                    const float ua = uni_ready(q);
                     count(MCD_C_MOLLER_TRIES);
                     const float r = fdiv(eps, 1.f - eps);
                     const float gv = 1.f + r * r + gg * gg * eps * eps - c * r;
                     if (ua * 2.25f <= gv) break;
                 }
-                const float ph = uni(q);
+                const float ph = uni_ready(q);
                 const float cp = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
                 const float tn = T - eps * T;      // primary keeps exactly T - W
                 const float wd = T - tn;
