@@ -42,8 +42,8 @@ sys.path.insert(0, ROOT)
 # of each workload divided by 2e5 (profiles/transport_lockstep_valu.md).  Each
 # VALU instruction of that path is one lane-op of the history's own work.
 PATH_LANE_OPS = {
-    "g6mv_wbw_61x61x60": 3619792724 / 200_000,     # 18099.0
-    "e20_wlw_32x32x30": 13938401861 / 200_000,     # 69692.0
+    "g6mv_wbw_61x61x60": 3464737789 / 200_000,     # 17323.7
+    "e20_wlw_32x32x30": 13295921535 / 200_000,     # 66479.6
 }
 # Plain VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # = 3.93e13 lane-ops/s (one non-packed FP32/INT32 op per lane per cycle).
@@ -52,7 +52,7 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # and WRITE_SIZE, each scaled by its reading for a 1 GiB device copy
 # (profiles/transport_g6mv_hbm_traffic.md).
 TRAFFIC_BYTES_PER_HIST = {
-    "g6mv_wbw_61x61x60": (10874377.625 * 2.0 + 34754613.15625 * 1.0) * 1024 / 155871453,   # 371.2
+    "g6mv_wbw_61x61x60": (10870310.0625 * 2.0 + 34752579.53125 * 1.0) * 1024 / 155871405,   # 371.1
 }
 METRIC = "histories/s (6 MV photon, 20 MeV e-) at 1% sigma; p50/p99 dose-request latency"
 # The paper's Table 1 (Tesla C1060, FP32; DPM physics and a measured 6 MV
