@@ -38,9 +38,9 @@ int mcd_ctx::launch_shape(const mcd_opts* o, int n_mat, int* blocks, int* thread
     return MCD_OK;
 }
 
-int mcd_ctx::wave_schedule(const mcd_opts* o, Sched* sc)
+int mcd_ctx::wave_schedule(const mcd_opts* o, Sched* sc, int default_fetch_div)
 {
-    sc->fetch_div = o && o->sched_fetch_div ? o->sched_fetch_div : kDefaultFetchDiv;
+    sc->fetch_div = o && o->sched_fetch_div ? o->sched_fetch_div : default_fetch_div;
     sc->hard_div = o && o->sched_hard_div ? o->sched_hard_div : kDefaultHardDiv;
     sc->photon_div = o && o->sched_photon_div ? o->sched_photon_div : kDefaultPhotonDiv;
     if (sc->fetch_div < 1 || sc->fetch_div > 64 || sc->hard_div < 1 || sc->hard_div > 64 ||
@@ -251,7 +251,10 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
         return fail(MCD_E_INVAL, "history records need diagnostics and a single request");
     int rc = launch_shape(opts, tables[ph.tables].n_mat, &plan.blocks, &plan.threads);
     if (rc) return rc;
-    if ((rc = wave_schedule(opts, &plan.sched))) return rc;
+    bool photons_only = true;
+    for (int r = 0; r < n_req; ++r) photons_only = photons_only && srcs[r] && srcs[r]->particle == MCD_PHOTON;
+    if ((rc = wave_schedule(opts, &plan.sched, photons_only ? kDefaultFetchDivPhotons : kDefaultFetchDiv)))
+        return rc;
     plan.req.resize(n_req);
     plan.fin.resize(n_req);
     plan.nb.assign((size_t)n_req * kBatches, 0.0);
