@@ -24,9 +24,9 @@ DEFAULT_SPACE = {
 }
 # second stage, searched around the best launch options
 SCHED_SPACE = {
-    "sched_fetch_div": (3, 4, 6),
-    "sched_hard_div": (16, 32),
-    "sched_photon_div": (4, 8),
+    "sched_fetch_div": (3, 4),
+    "sched_hard_div": (8, 24),
+    "sched_photon_div": (2, 6),
 }
 CACHE_ENV = "MCDOSE_TUNE_CACHE"
 

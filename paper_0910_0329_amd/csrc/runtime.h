@@ -26,11 +26,17 @@ constexpr int kLdsPerCu = 160 * 1024;
 constexpr int kExtraCycles = 8;     // claim counters kept beyond the planned cycles
 constexpr int kMaxBatch = 4096;
 constexpr int kDefaultFetchDiv = 4;
-// Regrouped launches whose sources are all photons fetch at 1/3: their
-// histories end more often per step, and fetch steps with more lanes pay off
-// (measured: 20 cm of lung +22%, the other photon workloads within 1%;
-// electron workloads lose 3-4% at 1/3 and keep 1/4).
-constexpr int kDefaultFetchDivPhotons = 3;
+// Wave-schedule defaults of the regrouped kernel, by the kind of its sources
+// (swept on the 6 MV and 20 MeV workloads): photon-only launches fetch at
+// 1/3 (their histories end often, and fuller fetch steps pay off), sample
+// hard events at 1/24 and fly photons once they are half the electrons;
+// launches with electron or positron sources fetch at 1/4, sample hard
+// events at 1/8 and fly photons at a sixth of the electrons.
+struct SchedDefaults {
+    int fetch_div, hard_div, photon_div;
+};
+constexpr SchedDefaults kSchedPhotonSources{3, 24, 2};
+constexpr SchedDefaults kSchedChargedSources{4, 8, 6};
 constexpr int kDefaultHardDiv = 16;
 constexpr int kDefaultPhotonDiv = 4;
 
@@ -211,7 +217,9 @@ struct mcd_ctx {
     int ensure_tallies(int64_t nv, hipStream_t s);
     int ensure_stage(int64_t nv, hipStream_t s);
     int launch_shape(const mcd_opts* o, int n_mat, int* blocks, int* threads);
-    int wave_schedule(const mcd_opts* o, mcd::Sched* sc, int default_fetch_div = mcd::kDefaultFetchDiv);
+    int wave_schedule(const mcd_opts* o, mcd::Sched* sc,
+                      mcd::SchedDefaults d = {mcd::kDefaultFetchDiv, mcd::kDefaultHardDiv,
+                                              mcd::kDefaultPhotonDiv});
     void fill_geom(mcd::KGeom& g, const mcd::PhantomRec& ph);
     int simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n, uint64_t seed,
                        uint32_t key, const mcd_opts* opts, mcd_result* out, hipStream_t s);

@@ -38,11 +38,11 @@ int mcd_ctx::launch_shape(const mcd_opts* o, int n_mat, int* blocks, int* thread
     return MCD_OK;
 }
 
-int mcd_ctx::wave_schedule(const mcd_opts* o, Sched* sc, int default_fetch_div)
+int mcd_ctx::wave_schedule(const mcd_opts* o, Sched* sc, SchedDefaults d)
 {
-    sc->fetch_div = o && o->sched_fetch_div ? o->sched_fetch_div : default_fetch_div;
-    sc->hard_div = o && o->sched_hard_div ? o->sched_hard_div : kDefaultHardDiv;
-    sc->photon_div = o && o->sched_photon_div ? o->sched_photon_div : kDefaultPhotonDiv;
+    sc->fetch_div = o && o->sched_fetch_div ? o->sched_fetch_div : d.fetch_div;
+    sc->hard_div = o && o->sched_hard_div ? o->sched_hard_div : d.hard_div;
+    sc->photon_div = o && o->sched_photon_div ? o->sched_photon_div : d.photon_div;
     if (sc->fetch_div < 1 || sc->fetch_div > 64 || sc->hard_div < 1 || sc->hard_div > 64 ||
         sc->photon_div < 1 || sc->photon_div > 64)
         return fail(MCD_E_INVAL, "opts: sched_fetch_div, sched_hard_div, sched_photon_div in [0, 64]");
@@ -253,7 +253,7 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
     if (rc) return rc;
     bool photons_only = true;
     for (int r = 0; r < n_req; ++r) photons_only = photons_only && srcs[r] && srcs[r]->particle == MCD_PHOTON;
-    if ((rc = wave_schedule(opts, &plan.sched, photons_only ? kDefaultFetchDivPhotons : kDefaultFetchDiv)))
+    if ((rc = wave_schedule(opts, &plan.sched, photons_only ? kSchedPhotonSources : kSchedChargedSources)))
         return rc;
     plan.req.resize(n_req);
     plan.fin.resize(n_req);
