@@ -52,7 +52,7 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # and WRITE_SIZE, each scaled by its reading for a 1 GiB device copy
 # (profiles/transport_g6mv_hbm_traffic.md).
 TRAFFIC_BYTES_PER_HIST = {
-    "g6mv_wbw_61x61x60": (10870310.0625 * 2.0 + 34752579.53125 * 1.0) * 1024 / 155871405,   # 371.1
+    "g6mv_wbw_61x61x60": (11386401.8125 * 2.0 + 34976274.59375 * 1.0) * 1024 / 155871405,   # 379.4
 }
 METRIC = "histories/s (6 MV photon, 20 MeV e-) at 1% sigma; p50/p99 dose-request latency"
 # The paper's Table 1 (Tesla C1060, FP32; DPM physics and a measured 6 MV
