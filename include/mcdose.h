@@ -158,7 +158,7 @@ typedef struct {
      * least 1/fetch_div of the wave's live lanes need one, sampling hard
      * events when 1/hard_div wait for it, photon flights when photons are at
      * least electrons/photon_div; else electron segments.  1..64, 0 = default:
-     * plain kernel (4, 16, 4); regrouped kernel (3, 24, 2) when every source
+     * plain kernel (3, 24, 2); regrouped kernel (3, 24, 2) when every source
      * is a photon source, else (4, 8, 6). */
     int32_t sched_fetch_div;
     int32_t sched_hard_div;

@@ -25,20 +25,19 @@ constexpr int kDefaultChunkPerLane = 16;
 constexpr int kLdsPerCu = 160 * 1024;
 constexpr int kExtraCycles = 8;     // claim counters kept beyond the planned cycles
 constexpr int kMaxBatch = 4096;
-constexpr int kDefaultFetchDiv = 4;
-// Wave-schedule defaults of the regrouped kernel, by the kind of its sources
-// (swept on the 6 MV and 20 MeV workloads): photon-only launches fetch at
-// 1/3 (their histories end often, and fuller fetch steps pay off), sample
-// hard events at 1/24 and fly photons once they are half the electrons;
-// launches with electron or positron sources fetch at 1/4, sample hard
-// events at 1/8 and fly photons at a sixth of the electrons.
+// Wave-schedule defaults (fetch_div, hard_div, photon_div), swept on the 6 MV
+// and 20 MeV workloads.  The regrouped kernel's depend on the kind of its
+// sources: photon-only launches fetch at 1/3 (their histories end often, and
+// fuller fetch steps pay off), sample hard events at 1/24 and fly photons
+// once they are half the electrons; launches with electron or positron
+// sources fetch at 1/4, sample hard events at 1/8 and fly photons at a sixth
+// of the electrons.  The plain kernel does best at (3, 24, 2) for both.
 struct SchedDefaults {
     int fetch_div, hard_div, photon_div;
 };
 constexpr SchedDefaults kSchedPhotonSources{3, 24, 2};
 constexpr SchedDefaults kSchedChargedSources{4, 8, 6};
-constexpr int kDefaultHardDiv = 16;
-constexpr int kDefaultPhotonDiv = 4;
+constexpr SchedDefaults kSchedPlain{3, 24, 2};
 
 // Small per-run device block: energy balance, counters, error flag, work
 // counter and finalisation reductions of the plain kernel.
@@ -217,9 +216,7 @@ struct mcd_ctx {
     int ensure_tallies(int64_t nv, hipStream_t s);
     int ensure_stage(int64_t nv, hipStream_t s);
     int launch_shape(const mcd_opts* o, int n_mat, int* blocks, int* threads);
-    int wave_schedule(const mcd_opts* o, mcd::Sched* sc,
-                      mcd::SchedDefaults d = {mcd::kDefaultFetchDiv, mcd::kDefaultHardDiv,
-                                              mcd::kDefaultPhotonDiv});
+    int wave_schedule(const mcd_opts* o, mcd::Sched* sc, mcd::SchedDefaults d);
     void fill_geom(mcd::KGeom& g, const mcd::PhantomRec& ph);
     int simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n, uint64_t seed,
                        uint32_t key, const mcd_opts* opts, mcd_result* out, hipStream_t s);

@@ -97,7 +97,7 @@ int mcd_ctx::simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n_h
     rc = launch_shape(opts, tables[ph.tables].n_mat, &blocks, &threads);
     if (rc) return rc;
     Sched sc;
-    if ((rc = wave_schedule(opts, &sc))) return rc;
+    if ((rc = wave_schedule(opts, &sc, kSchedPlain))) return rc;
     const bool diag = opts && opts->diagnostics;
     const bool accumulate = opts && opts->accumulate;
     if (opts && opts->history_records && !diag)
