@@ -191,8 +191,9 @@ struct Transport {
     // uniforms left, the most a flight, a segment or a particle start draws
     // outside the rejection loops; every lane with a free slot then refills
     // at the same time, so the rounds run for many lanes at once instead of
-    // for a few lanes at almost every step.  Draws beyond the ring refill
-    // in uni().
+    // for a few lanes at almost every step.  After it every lane holds at
+    // least two words, which those draws take with uni_ready; later draws
+    // check the ring (uni, or ensure once per rejection-loop try).
     DEV void prefetch(Part& q)
     {
         const bool slot = (q.d >> 2) + 1u >= q.g;
