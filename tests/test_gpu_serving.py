@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 from paper_0910_0329_amd.inputs import configs, phantoms, sources
-from paper_0910_0329_amd.inputs.sources import ELECTRON, PHOTON
+from paper_0910_0329_amd.inputs.sources import ELECTRON, PHOTON, POSITRON
 
 pytestmark = pytest.mark.gpu
 
@@ -97,6 +97,26 @@ def test_served_equals_standalone(eng, pool):
         ref = standalone(eng, pool, it)
         same(o, ref, pool[it[0]][1])
         assert o["latency_ms"] > 0
+
+
+def test_served_with_refined_tables_equals_standalone(eng):
+    """A phantom on tables with every refinement: the serving loop runs the
+    kernels built with the refinement code, as the blocking call does, and
+    gives the same result."""
+    from paper_0910_0329_amd.inputs import tables
+    thr = eng.load_materials(tables.standard_blob("refined"))
+    ph = phantoms.random_field_phantom(24, 0.5, seed=59, nz=20)
+    pid = eng.load_phantom(ph, thr)
+    items = [(g6mv(ph, 4.0), 60_000, 3, 1), (sources.pencil(POSITRON, 12.0, *ph.centre_xy()), 3_000, 3, 2)]
+    log("case serve refined tables")
+    eng.serve_configure(epoch_histories=20000, regroup=2)
+    tickets = [eng.submit(pid, src, n, seed, key) for src, n, seed, key in items]
+    outs = [eng.wait(t, n_vox=ph.n_vox) for t in tickets]
+    for o, (src, n, seed, key) in zip(outs, items):
+        ref = eng.simulate(pid, src, n, seed, key, n_vox=ph.n_vox, regroup=2)
+        same(o, ref, ph)
+    eng.unload_phantom(pid)
+    eng.unload_materials(thr)
 
 
 def test_served_matches_oracle(eng, blob, pool):
