@@ -164,8 +164,13 @@ def make_source(src) -> Source:
 
 
 def make_opts(**kw) -> Opts:
+    """mcd_opts from keyword arguments named after its fields; an unknown name
+    is an error (a ctypes structure would otherwise take it silently)."""
     o = Opts()
+    names = {f[0] for f in Opts._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown option {k!r}; mcd_opts has {sorted(names)}")
         setattr(o, k, v)
     return o
 
