@@ -226,7 +226,13 @@ int mcd_unload_phantom(mcd_ctx* ctx, int32_t phantom);
  * stack, dose collection).  seed and request_key key the Philox4x32-10 streams
  * (seed < 2^32, request_key < 2^32, first_history + n_histories <= 2^32).
  * Blocking: returns when the results are in `out`.  hip_stream may be a
- * hipStream_t (e.g. torch's current stream) or NULL for the context's stream. */
+ * hipStream_t (e.g. torch's current stream) or NULL for the context's stream.
+ * The caller owns every buffer in `out` (host or device per out->on_device).
+ * Errors: MCD_E_INVAL (arguments, options), MCD_E_NOTFOUND (handle),
+ * MCD_E_NOMEM (HBM budget), MCD_E_OVERFLOW (particle stack or local counter:
+ * raise stack_depth / tally_slots), MCD_E_DEVICE (HIP error); mcd_last_error
+ * gives the message.  On error the scalar fields of `out` are untouched;
+ * device-resident dose and sigma buffers may hold partial values. */
 int mcd_simulate(mcd_ctx* ctx, int32_t phantom, const mcd_source* src, uint64_t n_histories,
                  uint64_t seed, uint32_t request_key, const mcd_opts* opts, mcd_result* out,
                  void* hip_stream);
