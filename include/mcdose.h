@@ -277,9 +277,11 @@ enum { MCD_QUEUED = 0, MCD_ADMITTED = 1, MCD_RUNNING = 2, MCD_DONE = 3, MCD_FAIL
        MCD_CANCELED = 5 };
 
 typedef struct {
-    mcd_opts opts;              /* launch options of the epochs: block_size, grid_blocks,
-                                   stack_depth, chunk_per_lane, regroup, tally_fp32; the
-                                   others must be 0 (kernel: MCD_KERNEL_REGROUPED) */
+    mcd_opts opts;              /* launch options of the epochs (block_size, grid_blocks,
+                                   stack_depth, chunk_per_lane, regroup, tally_fp32,
+                                   diagnostics, sched_*, refined_build); first_history,
+                                   accumulate, history_records, lockstep, use_graph and
+                                   tally_slots must be 0, kernel MCD_KERNEL_REGROUPED */
     uint64_t epoch_histories;   /* histories per epoch over all its requests, 0 = two cycles'
                                    worth (2 x lanes x chunk_per_lane) */
     int32_t max_active;         /* admitted requests at most, 0 = 4096 */

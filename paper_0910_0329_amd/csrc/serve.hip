@@ -415,8 +415,8 @@ static int check_config(mcd_ctx* c, const mcd_serve_config* cfg)
     const mcd_opts& o = cfg->opts;
     if (o.first_history || o.accumulate || o.history_records || o.lockstep || o.use_graph ||
         o.kernel != MCD_KERNEL_REGROUPED || o.tally_slots)
-        return c->fail(MCD_E_INVAL, "serve config: only block_size, grid_blocks, stack_depth, "
-                                    "chunk_per_lane, regroup, tally_fp32 and diagnostics may be set");
+        return c->fail(MCD_E_INVAL, "serve config: first_history, accumulate, history_records, lockstep, "
+                                    "use_graph and tally_slots must be 0 and kernel regrouped");
     if (o.regroup < 0 || o.regroup > 2) return c->fail(MCD_E_INVAL, "serve config: regroup must be 0, 1 or 2");
     if (o.stack_depth && (o.stack_depth < 4 || o.stack_depth > 4096))
         return c->fail(MCD_E_INVAL, "serve config: stack_depth in [4, 4096]");
