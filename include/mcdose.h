@@ -316,9 +316,12 @@ int mcd_submit(mcd_ctx* ctx, int32_t phantom, const mcd_source* src, uint64_t n_
                uint64_t seed, uint32_t request_key, uint64_t* out_ticket);
 
 /* Queues a request that stops at a target uncertainty: its histories run in
- * epochs as for mcd_submit, and after every epoch it took part in the
- * request is finalised; it completes once sigma-bar <= sigma_bar_target (and
- * Dmax > 0, at least 1000 histories) or when n_max histories have run.  The
+ * epochs as for mcd_submit, and the request is finalised at checkpoints
+ * (after the epoch that reaches 95% of the histories its last sigma-bar
+ * projects for the target by the N^-1/2 law, at most four times the
+ * histories it has); it completes once sigma-bar <= sigma_bar_target (and
+ * Dmax > 0, at least 1000 histories) at a checkpoint, or when n_max
+ * histories have run.  The
  * result equals mcd_simulate of the same request with N = the histories it
  * ran (mcd_result.n_histories), up to FP64 summation order.
  * 0 < sigma_bar_target < 1, 1000 <= n_max < 2^32. */

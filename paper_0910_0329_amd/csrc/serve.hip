@@ -38,6 +38,7 @@ struct Request {
     mcd_source src{};
     uint64_t n = 0, done = 0;          // n: histories to run (adaptive: at most)
     double target = 0.0;               // adaptive: sigma-bar to reach (0: run all n)
+    uint64_t next_check = 0;           // adaptive: finalise once done reaches it
     uint32_t seed = 0, key = 0;
     int state = MCD_QUEUED;
     int status = MCD_OK;
@@ -56,6 +57,21 @@ struct Request {
 };
 
 constexpr uint64_t kAdaptiveMin = 1000;   // histories before an adaptive request may stop
+
+// Next checkpoint of an adaptive request that has run d histories with
+// sigma-bar sb (Dmax > 0 when have_dose).  sigma-bar falls as N^-1/2, so the
+// target is due near N* = d (sb / target)^2; the next finalisation comes at
+// 95% of that, at most four times d, so a request is finalised a handful of
+// times instead of after every epoch, and stops within one epoch slice of
+// where a finalisation after every epoch would stop it.
+uint64_t next_checkpoint(uint64_t d, double sb, double target, bool have_dose)
+{
+    if (d < kAdaptiveMin) return kAdaptiveMin;
+    if (!have_dose || !(sb > 0.0)) return 2 * d;
+    const double due = 0.95 * (double)d * (sb / target) * (sb / target);
+    const double next = std::min(due, 4.0 * (double)d);
+    return std::max<uint64_t>(d + 1, (uint64_t)next);
+}
 
 double ms_between(Clock::time_point a, Clock::time_point b)
 {
@@ -277,9 +293,11 @@ static void run_epoch(mcd_ctx* c, mcd_server* S)
     // adaptive ones (their sigma-bar decides whether they finish)
     std::vector<size_t> order(n);
     for (size_t i = 0; i < n; ++i) order[i] = i;
-    std::stable_partition(order.begin(), order.end(), [&](size_t i) {
-        return batch[i]->done + slice[i] == batch[i]->n || batch[i]->target > 0.0;
-    });
+    auto finalised = [&](size_t i) {
+        const Request* r = batch[i];
+        return r->done + slice[i] == r->n || (r->target > 0.0 && r->done + slice[i] >= r->next_check);
+    };
+    std::stable_partition(order.begin(), order.end(), finalised);
     std::vector<const mcd_source*> srcs(n);
     std::vector<uint64_t> ns(n);
     std::vector<uint32_t> keys(n);
@@ -298,7 +316,7 @@ static void run_epoch(mcd_ctx* c, mcd_server* S)
         extra[j].dose = r->dose;
         extra[j].sigma = r->sigma;
         extra[j].nb_prior = r->nb;
-        if (r->done + ns[j] == r->n || r->target > 0.0) ++n_fin;
+        if (finalised(order[j])) ++n_fin;
     }
     mcd_opts o = S->cfg.opts;
     RegroupPlan plan;
@@ -373,6 +391,8 @@ static void run_epoch(mcd_ctx* c, mcd_server* S)
         if ((int)j < n_fin) {
             r->dmax = red[3 * j];
             r->sigma_bar = red[3 * j + 2] > 0 ? red[3 * j + 1] / red[3 * j + 2] : 0.0;
+            if (r->target > 0.0)
+                r->next_check = next_checkpoint(r->done, r->sigma_bar, r->target, r->dmax > 0.0);
         }
         if (ends[j]) end_request(S, r, MCD_DONE, MCD_OK, "");
         else r->state = MCD_ADMITTED;
