@@ -282,8 +282,8 @@ typedef struct {
                                    diagnostics, sched_*, refined_build); first_history,
                                    accumulate, history_records, lockstep, use_graph and
                                    tally_slots must be 0, kernel MCD_KERNEL_REGROUPED */
-    uint64_t epoch_histories;   /* histories per epoch over all its requests, 0 = two cycles'
-                                   worth (2 x lanes x chunk_per_lane) */
+    uint64_t epoch_histories;   /* histories per epoch over all its requests, 0 = four cycles'
+                                   worth (4 x lanes x chunk_per_lane) */
     int32_t max_active;         /* admitted requests at most, 0 = 4096 */
     int32_t reserved;
     uint64_t memory_limit;      /* bytes of request memory (tallies, dose, sigma) held at once,

@@ -277,7 +277,11 @@ static void run_epoch(mcd_ctx* c, mcd_server* S)
         if (c->launch_shape(&S->cfg.opts, c->tables[ph.tables].n_mat, &blocks, &threads) != MCD_OK)
             blocks = threads = 1;
         const int cpl = S->cfg.opts.chunk_per_lane ? S->cfg.opts.chunk_per_lane : kDefaultChunkPerLane;
-        budget = 2 * (uint64_t)blocks * threads * (uint64_t)cpl;
+        // four cycles' worth: each epoch ends with a drain in which few lanes
+        // are busy, and on a loaded server longer epochs pay for fewer of them
+        // (the 20 req/s mixed stream measured +3.5% and lower p50 and p99
+        // against two cycles; eight cycles add 1% more)
+        budget = 4 * (uint64_t)blocks * threads * (uint64_t)cpl;
     }
     std::sort(batch.begin(), batch.end(),
               [](const Request* a, const Request* b) { return a->n - a->done < b->n - b->done; });
