@@ -382,6 +382,28 @@ def test_lean_build_runs_the_same_histories(eng, blob, th, kernel, particle):
         assert a["cnt"][k] == pytest.approx(b["cnt"][k], rel=5e-3, abs=5), k
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_all_lanes_one_voxel_exact_sum(eng, th, kernel):
+    """Atomic exactness under full contention: photons below the photon
+    cutoff are absorbed where they enter, so every history adds the same
+    E0 = 2^-5 MeV to one voxel.  Every partial sum is then exact in FP32 and
+    FP64, and the tally must hold N E0 exactly, with nothing elsewhere."""
+    ph = phantoms.homogeneous(8, 8, 8, 1.0)
+    x, y = ph.centre_xy()
+    n = 4_000_000
+    e0 = 2.0 ** -5
+    pid = eng.load_phantom(ph, th)
+    g = eng.simulate(pid, sources.pencil(PHOTON, e0, x + 0.1, y + 0.1), n, 7, n_vox=ph.n_vox,
+                     want_tallies=True, **kopt(kernel))
+    eng.unload_phantom(pid)
+    S = g["S"].cpu().numpy()
+    v = np.flatnonzero(S)
+    assert len(v) == 1
+    assert S[v[0]] == n * e0
+    assert v[0] == 4 * 8 + 4                   # ix = iy = 4, iz = 0 (x fastest)
+    assert g["bal"]["E_local"] == n * e0 and g["bal"]["E_src"] == n * e0
+
+
 def test_batch_equals_separate_runs(eng, th):
     """Several beams with uneven history counts in one regrouped launch give each
     beam the result of its own run (same keys); repeated graph replays agree."""
