@@ -468,6 +468,34 @@ def test_field_wider_than_the_phantom(eng, blob, th, kernel):
     assert f > 0.95
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_top_of_the_history_range(eng, blob, th, kernel):
+    """Histories [2^32 - n, 2^32), the last indices a run may take, match the
+    oracle's; one history past the end is refused."""
+    import torch
+    from paper_0910_0329_amd.mcdose import E_INVAL, McdError
+    w = configs.photon_6mv_wbw(100_000)
+    n = w.n_histories
+    first = 2 ** 32 - n
+    pid = eng.load_phantom(w.phantom, th)
+    log(f"case top of range first={first} n={n} kernel={kernel}")
+    hist = torch.zeros(n * 4, dtype=torch.float64, device="cuda")
+    g = eng.simulate(pid, w.source, n, w.seed, n_vox=w.phantom.n_vox, want_tallies=True,
+                     first_history=first, history_records=hist, **kopt(kernel))
+    g["hist"] = np.frombuffer(hist.cpu().numpy().tobytes(), dtype=oracle.HISTORY_DTYPE)
+    with pytest.raises(McdError) as ei:
+        eng.simulate(pid, w.source, n, w.seed, n_vox=w.phantom.n_vox, first_history=first + 1,
+                     **kopt(kernel))
+    assert ei.value.status == E_INVAL
+    eng.unload_phantom(pid)
+    ref = oracle.simulate(blob, w.phantom, w.source, n, w.seed, first=first, history=True, groups=True)
+    check_dose(w.phantom, g, ref, n, kernel)
+    check_balance(g, ref)
+    f = match_fraction(g, ref)
+    log(f"  history match fraction {f:.4f}")
+    assert f > 0.9
+
+
 def test_batch_equals_separate_runs(eng, th):
     """Several beams with uneven history counts in one regrouped launch give each
     beam the result of its own run (same keys); repeated graph replays agree."""
