@@ -13,9 +13,14 @@
  * Conventions
  *   - Units: cm, MeV, g, g/cm^3; dose in Gy per source history.
  *   - Voxel arrays are x-fastest: v = (k * ny + j) * nx + i.
- *   - Every function returns an mcd_status (0 = OK, negative = error); on
- *     error no output is written and mcd_last_error() explains it.  No C++
- *     exception or abort crosses this interface.
+ *   - Every function returns an mcd_status (0 = OK, negative = error) and
+ *     mcd_last_error() explains an error.  On error no handle (mcd_create
+ *     sets its handle to NULL), host result field or host array is written,
+ *     except that a HIP failure during the copy of results (MCD_E_DEVICE) may
+ *     leave output arrays partly written; device buffers the caller passed as
+ *     outputs (dose and sigma written in place, history records) may hold
+ *     partial data after any error.  No C++ exception or abort crosses this
+ *     interface.
  *   - Host pointers are read during the call and may be freed on return.
  *   - Device pointers are HIP device addresses on the context's device.
  *   - Calls on one context may come from several threads: blocking runs and
