@@ -236,11 +236,12 @@ def main():
     line["electron_20MeV"] = electron
 
     # ------------------------------------------------------------ table variants
-    # physics refinements behind table flags: emission angles, the density
-    # effect, Rayleigh scattering, the second-moment hinge, Bhabha events for
-    # positrons, and all of them together
+    # physics refinements in the tables: emission angles, the density effect,
+    # per-element screening, Rayleigh scattering, the second-moment hinge,
+    # Bhabha events for positrons, and all of them but per-element screening
+    # together
     variants = {}
-    for variant in ("angular", "density", "rayleigh", "hinge2", "bhabha", "refined"):
+    for variant in ("angular", "density", "elements", "rayleigh", "hinge2", "bhabha", "refined"):
         thv = eng.load_materials(tables.standard_blob(variant))
         cur = {}
         for w, n in ((wg, 20_000_000), (we, 4_000_000)):

@@ -108,6 +108,21 @@ MATERIALS = (
 )
 MAT_AIR, MAT_LUNG, MAT_WATER, MAT_BONE = range(4)
 
+# Elemental compositions (Z, A in g/mol, mass fraction) behind the effective
+# atoms above, used where a quantity is summed element by element.  Air is
+# dry air near sea level and water is H2O (their sums reproduce the effective
+# atoms to 0.1%).  The bone of these synthetic tables is no tabulated tissue:
+# its H, C, O and Ca fractions are the ones whose sum of w, w Z/A, w Z^2/A and
+# w Z^4/A equal 1 and the bone atom's Z/A, B and P.
+COMPOSITIONS = {
+    "air": ((6, 12.0107, 0.000124), (7, 14.0067, 0.755268), (8, 15.9994, 0.231781),
+            (18, 39.948, 0.012827)),
+    "lung": ((1, 1.00794, 0.111894), (8, 15.9994, 0.888106)),
+    "water": ((1, 1.00794, 0.111894), (8, 15.9994, 0.888106)),
+    "bone": ((1, 1.00794, 0.030593), (6, 12.0107, 0.036078), (8, 15.9994, 0.674474),
+             (20, 40.078, 0.258855)),
+}
+
 
 def energy_grid() -> np.ndarray:
     """E_i = E_min (E_max/E_min)^(i/511), i = 0..511 (MeV)."""
@@ -328,12 +343,18 @@ def sigma_moller_hard(m: Material, t: float, w_cc: float) -> float:
     return N_A * m.zoa * 2.0 * math.pi * R_E ** 2 * MC2 / (beta2 * t) * br
 
 
-def screening_moliere(m: Material, t: float) -> float:
+def screening_charge(zs: float, t: float) -> float:
+    """Moliere's screening parameter of an atom of charge zs for an electron of
+    kinetic energy t: Thomas-Fermi radius 0.885 a0 zs^(-1/3), with his
+    correction factor 1.13 + 3.76 (alpha zs / beta)^2."""
     _, pc, beta2 = _kin(t)
     beta = math.sqrt(beta2)
-    zs = m.zs
     return 0.25 * (HBARC / (0.885 * A0 * pc)) ** 2 * zs ** (2.0 / 3.0) * (
         1.13 + 3.76 * (ALPHA * zs / beta) ** 2)
+
+
+def screening_moliere(m: Material, t: float) -> float:
+    return screening_charge(m.zs, t)
 
 
 def lambda1_inv(m: Material, t: float) -> float:
@@ -352,6 +373,30 @@ def lambda2_inv(m: Material, t: float) -> float:
     a = screening_moliere(m, t)
     k = (R_E * MC2 / (math.sqrt(beta2) * pc)) ** 2
     return N_A * m.ee * 2.0 * math.pi * k * 3.0 * ((1.0 + 2.0 * a) * math.log1p(1.0 / a) - 2.0)
+
+
+def lambda1_inv_elements(comp, t: float) -> float:
+    """1/(lambda1 rho) with each element screened by its own charge: the
+    screened-Rutherford transport cross section summed over the elements
+    (Z, A, w) of comp, each with the screening parameter of its Z."""
+    _, pc, beta2 = _kin(t)
+    k = (R_E * MC2 / (math.sqrt(beta2) * pc)) ** 2
+    acc = 0.0
+    for z, a_mol, w in comp:
+        a = screening_charge(float(z), t)
+        acc += w / a_mol * z * (z + 1) * (math.log1p(1.0 / a) - 1.0 / (1.0 + a))
+    return N_A * 2.0 * math.pi * k * acc
+
+
+def lambda2_inv_elements(comp, t: float) -> float:
+    """1/(lambda2 rho) summed element by element, as lambda1_inv_elements."""
+    _, pc, beta2 = _kin(t)
+    k = (R_E * MC2 / (math.sqrt(beta2) * pc)) ** 2
+    acc = 0.0
+    for z, a_mol, w in comp:
+        a = screening_charge(float(z), t)
+        acc += w / a_mol * z * (z + 1) * ((1.0 + 2.0 * a) * math.log1p(1.0 / a) - 2.0)
+    return N_A * 2.0 * math.pi * k * 3.0 * acc
 
 
 def solve_a_hinge(kappa_step: float) -> float:
@@ -419,8 +464,12 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
                   moment exp(-s/lambda2) as well as the first;
       "bhabha"    standard tables; positrons take their own stopping power
                   and range and hard Bhabha events instead of Moller ones;
-      "refined"   every refinement above: angular, density, rayleigh, hinge2,
-                  bhabha.
+      "elements"  standard, with the elastic transport cross sections 1/lambda1
+                  and 1/lambda2 summed element by element over COMPOSITIONS,
+                  each element screened by its own charge (tables only; the
+                  blob carries no flag for it);
+      "refined"   every refinement above except "elements": angular, density,
+                  rayleigh, hinge2, bhabha.
     The positron quantities are tabulated for every variant.
     """
     e = energy_grid()
@@ -441,14 +490,20 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
         flags |= FLAG_HINGE2
     elif variant == "bhabha":
         flags |= FLAG_BHABHA
+    elif variant == "elements":
+        pass
     elif variant == "refined":
         flags |= FLAG_ANGULAR | FLAG_DENSITY | FLAG_RAYLEIGH | FLAG_HINGE2 | FLAG_BHABHA
     elif variant != "standard":
         raise ValueError(f"unknown table variant {variant!r}")
     w_cc = None if flags & FLAG_NO_HARD else E_ABS_E
     w_cr = None if flags & FLAG_NO_HARD else E_ABS_G
+    per_element = variant == "elements"
     for mi, m in enumerate(materials):
         dens = bool(flags & FLAG_DENSITY)
+        if per_element and m.name not in COMPOSITIONS:
+            raise ValueError(f"no elemental composition for material {m.name!r}")
+        comp = COMPOSITIONS.get(m.name)
 
         def lr(t, m=m, dens=dens):
             return l_col(m, t, w_cc, dens) + l_rad(m, t, w_cr)
@@ -462,8 +517,12 @@ def build_tables(materials=MATERIALS, variant: str = "standard", kappa_step: flo
                 if flags & FLAG_RAYLEIGH:
                     data[mi, Q_MU_R, i] = mu_rayleigh(m, ei)
             data[mi, Q_MU_PE, i] = mu_photo(m, ei)
-            data[mi, Q_LAMBDA1_INV, i] = lambda1_inv(m, ei)
-            data[mi, Q_LAMBDA2_INV, i] = lambda2_inv(m, ei)
+            if per_element:
+                data[mi, Q_LAMBDA1_INV, i] = lambda1_inv_elements(comp, ei)
+                data[mi, Q_LAMBDA2_INV, i] = lambda2_inv_elements(comp, ei)
+            else:
+                data[mi, Q_LAMBDA1_INV, i] = lambda1_inv(m, ei)
+                data[mi, Q_LAMBDA2_INV, i] = lambda2_inv(m, ei)
             if not flags & FLAG_NO_HARD:
                 data[mi, Q_SIGMA_M, i] = sigma_moller_hard(m, ei, E_ABS_E)
                 data[mi, Q_SIGMA_B, i] = sigma_brems_hard(m, ei, E_ABS_G)

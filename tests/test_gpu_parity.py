@@ -209,6 +209,27 @@ def test_density_effect_tables_match_oracle(eng, kernel):
 
 
 @pytest.mark.parametrize("kernel", ("plain", "regrouped"))
+@pytest.mark.parametrize("middle", ("lung", "bone"))
+def test_per_element_screening_tables_match_oracle(eng, kernel, middle):
+    """Tables whose elastic cross sections screen each element by its own
+    charge: the same transport code on different 1/lambda1 (hinge spacing)
+    and 1/lambda2, 20 MeV electrons on the paper's slab phantoms."""
+    from paper_0910_0329_amd.inputs import tables
+    blob = tables.standard_blob("elements")
+    the = eng.load_materials(blob)
+    w = configs.paper_workload(ELECTRON, middle, 4_000)
+    log(f"case per-element screening tables {w.name} kernel={kernel}")
+    g, ref = run_both(eng, blob, the, w.phantom, w.source, w.n_histories, w.seed, kernel=kernel)
+    check_dose(w.phantom, g, ref, w.n_histories, kernel)
+    check_balance(g, ref)
+    f = match_fraction(g, ref)
+    log(f"  history match fraction {f:.4f}")
+    assert f > 0.8
+    assert g["cnt"]["hinges"] == pytest.approx(ref["cnt"]["hinges"], rel=0.02)
+    eng.unload_materials(the)
+
+
+@pytest.mark.parametrize("kernel", ("plain", "regrouped"))
 @pytest.mark.parametrize("variant,particle,e,n", [("rayleigh", PHOTON, 0.15, 60_000),
                                                   ("refined", PHOTON, 0.25, 60_000),
                                                   ("refined", PHOTON, 6.0, 30_000)])

@@ -135,6 +135,89 @@ def test_second_transport_cross_section_against_quadrature():
     assert np.all(np.diff(rs) > 0)
 
 
+def _comp_sums(comp):
+    w = sum(x for _, _, x in comp)
+    zoa = sum(x * z / a for z, a, x in comp)
+    b = sum(x * z * z / a for z, a, x in comp)
+    ee = sum(x * z * (z + 1) / a for z, a, x in comp)
+    p = sum(x * z ** 4 / a for z, a, x in comp)
+    return w, zoa, b, ee, p
+
+
+def test_compositions_reproduce_the_effective_atoms():
+    """Each material's elements sum to the effective atom it stands for:
+    mass fractions to 1, and w Z/A, w Z^2/A, w Z(Z+1)/A, w Z^4/A to its Z/A,
+    B, E and P (air and water within 0.1% from their standard compositions;
+    the fitted bone to 1e-4, the precision of the bone atom's E)."""
+    for m in T.MATERIALS:
+        w, zoa, b, ee, p = _comp_sums(T.COMPOSITIONS[m.name])
+        tol = 1e-4 if m.name == "bone" else 1e-3
+        assert w == pytest.approx(1.0, abs=1e-6)
+        for got, want in ((zoa, m.zoa), (b, m.b), (ee, m.ee), (p, m.p)):
+            assert got == pytest.approx(want, rel=tol), m.name
+        assert all(x > 0 for _, _, x in T.COMPOSITIONS[m.name])
+
+
+def test_single_element_per_element_screening_is_the_effective_atom():
+    """For a material of one element, screening element by element is the
+    effective-atom model (Z_s = B/(Z/A) = Z, E = Z(Z+1)/A): both transport
+    cross sections agree to rounding."""
+    for z, a in ((1, 1.00794), (8, 15.9994), (20, 40.078), (82, 207.2)):
+        m = T.Material("el", 1.0, z / a, 100.0, z * z / a, z * (z + 1) / a, z ** 4 / a)
+        comp = ((z, a, 1.0),)
+        for t in (0.2, 1.0, 20.0):
+            assert T.lambda1_inv_elements(comp, t) == pytest.approx(T.lambda1_inv(m, t), rel=1e-12)
+            assert T.lambda2_inv_elements(comp, t) == pytest.approx(T.lambda2_inv(m, t), rel=1e-12)
+
+
+def test_per_element_transport_cross_sections_against_quadrature():
+    """1/lambda1 and 1/lambda2 of a mixture: the screened-Rutherford DCS of each
+    element, Z(Z+1) with its own screening, weighted by w/A and integrated
+    numerically against 1 - cos and 1 - P2(cos)."""
+    for name in ("air", "water", "bone"):
+        comp = T.COMPOSITIONS[name]
+        for t in (0.2, 1.0, 20.0):
+            _, pc, beta2 = T._kin(t)
+            k = (T.R_E * T.MC2 / (math.sqrt(beta2) * pc)) ** 2
+            v1 = v2 = 0.0
+            for z, a_mol, w in comp:
+                a = T.screening_charge(float(z), t)
+
+                def dcs(x, a=a, z=z):           # per atom, in x = 1 - cos
+                    return 2 * math.pi * z * (z + 1) * k / (x + 2 * a) ** 2
+
+                def g1(x):
+                    return x * dcs(x)
+
+                def g2(x):
+                    c = 1.0 - x
+                    return (1.0 - 0.5 * (3 * c * c - 1)) * dcs(x)
+                # the integrands are of order k ~ 1e-25 cm^2: relative tolerance only
+                q = dict(points=[2 * a, 20 * a], epsabs=0.0, epsrel=1e-11, limit=400)
+                v1 += T.N_A * w / a_mol * integrate.quad(g1, 0.0, 2.0, **q)[0]
+                v2 += T.N_A * w / a_mol * integrate.quad(g2, 0.0, 2.0, **q)[0]
+            assert T.lambda1_inv_elements(comp, t) == pytest.approx(v1, rel=1e-8), (name, t)
+            assert T.lambda2_inv_elements(comp, t) == pytest.approx(v2, rel=1e-8), (name, t)
+
+
+def test_elements_variant_changes_only_the_elastic_quantities():
+    """The per-element tables differ from the standard ones in 1/lambda1 and
+    1/lambda2 only: by up to 12% at keV energies, where screening matters most,
+    and by under 2% above the 200 keV electron cutoff, where electrons are
+    transported."""
+    a = T.read_blob(T.standard_blob("elements"))
+    b = T.read_blob(T.standard_blob())
+    assert a.flags == b.flags == 0
+    for q in range(T.N_Q):
+        if q in (T.Q_LAMBDA1_INV, T.Q_LAMBDA2_INV):
+            r = a.data[:, q] / b.data[:, q]
+            assert np.all(np.abs(r - 1) < 0.13) and np.any(np.abs(r - 1) > 1e-3)
+            hi = a.energies >= T.E_ABS_E
+            assert np.all(np.abs(r[:, hi] - 1) < 0.02)
+        else:
+            assert np.array_equal(a.data[:, q], b.data[:, q]), T.QUANTITY_NAMES[q]
+
+
 def test_a_hinge_solves_lewis_first_moment():
     a = T.solve_a_hinge(0.1)
     assert a == pytest.approx(0.0143284, rel=1e-5)
