@@ -78,6 +78,9 @@ def parse():
                     help="only the headline steps (used for profiling the transport phase)")
     ap.add_argument("--lockstep-probe", action="store_true",
                     help="run one lockstep launch per workload (for SQ_INSTS_VALU) and exit")
+    ap.add_argument("--electron-only", action="store_true",
+                    help="only the 20 MeV pencil-beam steps of 1e7 histories, one JSON line "
+                         "(used for profiling the electron-source phase kernel)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy (calibrates FETCH_SIZE/WRITE_SIZE) and exit")
     return ap.parse_args()
@@ -142,6 +145,21 @@ def main():
 
     def run(w, p, n, **kw):
         return eng.simulate(p, w.source, n, w.seed, w.request_key, n_vox=w.phantom.n_vox, **kw)
+
+    if args.electron_only:
+        for _ in range(args.warmup):
+            run(we, pe, we.n_histories)
+        te, re_ = timed(lambda: run(we, pe, we.n_histories), args.steps)
+        pe_path = PATH_LANE_OPS[we.name]
+        k_s = re_["kernel_ms"] * 1e-3
+        print(json.dumps({"workload": we.name, "histories_per_step": we.n_histories, "steps": args.steps,
+                          "hist_per_s": we.n_histories / te, "kernel_ms": re_["kernel_ms"],
+                          "launches": re_["launches"],
+                          "per_launch_ms": re_["kernel_ms"] / max(re_["launches"], 1),
+                          "alu_frac": pe_path * we.n_histories / k_s / PEAK_LANE_OPS,
+                          "energy_balance_rel": closure(re_["bal"])}), flush=True)
+        eng.close()
+        return
 
     # ------------------------------------------------------------ headline
     pilot = run(wg, pg, wg.n_histories, kernel=KERNEL_PLAIN)
