@@ -1,4 +1,4 @@
-"""Request-stream driver of the serving loop: calibrates history counts for a
+"""Request-stream replay for the serving loop: calibrates history counts for a
 target uncertainty, replays timed arrivals against an Engine's mcd_submit /
 mcd_wait, and summarises latency and throughput.
 
