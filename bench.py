@@ -48,11 +48,12 @@ PATH_LANE_OPS = {
 # Plain VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # = 3.93e13 lane-ops/s (one non-packed FP32/INT32 op per lane per cycle).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-# HBM bytes per history of the photon transport phase: rocprofv3 FETCH_SIZE
-# and WRITE_SIZE, each scaled by its reading for a 1 GiB device copy
-# (profiles/transport_g6mv_hbm_traffic.md).
+# HBM bytes per history of the transport kernel: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, each scaled by its reading for a 1 GiB device copy
+# (profiles/transport_g6mv_hbm_traffic.md, profiles/transport_e20_wlw_hbm_traffic.md).
 TRAFFIC_BYTES_PER_HIST = {
     "g6mv_wbw_61x61x60": (11386401.8125 * 2.0 + 34976274.59375 * 1.0) * 1024 / 155871405,   # 379.4
+    "e20_wlw_32x32x30": (2615060.375 * 2.0 + 17980546.21875 * 1.0) * 1024 / 10_000_000,     # 2376.8
 }
 METRIC = "histories/s (6 MV photon, 20 MeV e-) at 1% sigma; p50/p99 dose-request latency"
 # The paper's Table 1 (Tesla C1060, FP32; DPM physics and a measured 6 MV
@@ -157,6 +158,7 @@ def main():
                           "launches": re_["launches"],
                           "per_launch_ms": re_["kernel_ms"] / max(re_["launches"], 1),
                           "alu_frac": pe_path * we.n_histories / k_s / PEAK_LANE_OPS,
+                          "traffic": TRAFFIC_BYTES_PER_HIST[we.name] * we.n_histories / max(re_["launches"], 1),
                           "energy_balance_rel": closure(re_["bal"])}), flush=True)
         eng.close()
         return
@@ -239,6 +241,11 @@ def main():
     pe_path = PATH_LANE_OPS.get(we.name)
     if pe_path:
         electron["pencil_1e7"]["alu_frac"] = pe_path * we.n_histories / (re_["kernel_ms"] * 1e-3) / PEAK_LANE_OPS
+    pe_tb = TRAFFIC_BYTES_PER_HIST.get(we.name)
+    if pe_tb:
+        # one launch per step in lane-stack mode: bytes per launch, and HBM rate
+        electron["pencil_1e7"]["traffic"] = pe_tb * we.n_histories / max(re_["launches"], 1)
+        electron["pencil_1e7"]["hbm_frac"] = pe_tb * we.n_histories / (re_["kernel_ms"] * 1e-3) / 8e12
     wf = configs.electron_20mev_point_field(we.phantom, 1_000_000)
     fpilot = run(wf, pe, wf.n_histories, kernel=KERNEL_PLAIN)
     n1f = int(math.ceil(wf.n_histories * (fpilot["sigma_bar"] / 0.01) ** 2))
