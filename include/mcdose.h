@@ -23,6 +23,8 @@
  *     interface.
  *   - Host pointers are read during the call and may be freed on return.
  *   - Device pointers are HIP device addresses on the context's device.
+ *     Entry points make that device current while they run and give the
+ *     calling thread back its own current device before returning.
  *   - Calls on one context may come from several threads: blocking runs and
  *     serving epochs take turns on the device; table and phantom loads wait
  *     for the run in progress.  mcd_destroy must not overlap other calls.

@@ -136,6 +136,29 @@ int run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_graph,
 // Records per particle queue for cycles of `chunk` new histories.
 unsigned int queue_capacity(uint64_t chunk);
 
+// Makes `dev` the calling thread's current HIP device for the guard's scope
+// and gives the caller back its own device afterwards, so that no entry point
+// changes the caller's HIP state.
+class DeviceGuard {
+public:
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+        ok_ = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev_ >= 0) (void)hipSetDevice(prev_);
+    }
+    DeviceGuard(const DeviceGuard&) = delete;
+    DeviceGuard& operator=(const DeviceGuard&) = delete;
+    bool ok() const { return ok_; }
+
+private:
+    int prev_ = -1;
+    bool ok_ = false;
+};
+
 // Mutex that hands itself over in request order (a ticket lock).  The serving
 // worker takes the device lock once per epoch and asks for it again at once;
 // with a plain mutex it can win every time and hold off a blocking call for

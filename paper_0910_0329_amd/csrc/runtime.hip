@@ -110,7 +110,8 @@ int mcd_create(int device, uint64_t hbm_budget_bytes, mcd_ctx** out)
     *out = nullptr;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MCD_E_INVAL;
-    if (hipSetDevice(device) != hipSuccess) return MCD_E_DEVICE;
+    mcd::DeviceGuard dg(device);
+    if (!dg.ok()) return MCD_E_DEVICE;
     mcd_ctx* c = new (std::nothrow) mcd_ctx();
     if (!c) return MCD_E_NOMEM;
     c->device = device;
@@ -148,7 +149,7 @@ int mcd_create(int device, uint64_t hbm_budget_bytes, mcd_ctx** out)
 int mcd_destroy(mcd_ctx* c)
 {
     if (!c) return MCD_E_INVAL;
-    (void)hipSetDevice(c->device);
+    mcd::DeviceGuard dg(c->device);
     (void)hipStreamSynchronize(c->stream);
     c->shutdown_serving();
     for (auto& t : c->tables)
@@ -328,7 +329,7 @@ int mcd_load_materials(mcd_ctx* c, const void* blob, size_t nbytes, int32_t* out
                                   ? hinge_law(ts.kappa_step, ts.a_hinge, q[9 * kNE + i] / q[4 * kNE + i])
                                   : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-    (void)hipSetDevice(c->device);
+    mcd::DeviceGuard dg(c->device);
     ts.bytes = ph.size() * sizeof(float4);
     void* dev[4] = {nullptr, nullptr, nullptr, nullptr};            // phot, elec, hinge, posi
     const void* host[4] = {ph.data(), el.data(), hl.data(), po.data()};
@@ -410,7 +411,7 @@ int mcd_unload_materials(mcd_ctx* c, int32_t t)
     for (auto& p : c->phantoms)
         if (p.live && p.tables == t) return c->fail(MCD_E_INVAL, "tables still used by a phantom");
     TableSet& ts = c->tables[t];
-    (void)hipSetDevice(c->device);
+    mcd::DeviceGuard dg(c->device);
     (void)hipDeviceSynchronize();
     c->release(ts.dev.phot, ts.bytes);
     c->release(ts.dev.elec, ts.bytes);
@@ -465,7 +466,7 @@ int mcd_load_phantom(mcd_ctx* c, const mcd_grid* g, const uint8_t* mat, const fl
     p.g = *g;
     p.tables = tables;
     p.nv = nv;
-    (void)hipSetDevice(c->device);
+    mcd::DeviceGuard dg(c->device);
     int rc = c->alloc((void**)&p.vox, (size_t)nv * sizeof(uint2), "phantom");
     if (rc) return rc;
     rc = c->alloc((void**)&p.maj, kNE * sizeof(float), "majorant");
@@ -495,7 +496,7 @@ int mcd_unload_phantom(mcd_ctx* c, int32_t ph)
     if (ph < 0 || ph >= (int32_t)c->phantoms.size() || !c->phantoms[ph].live) return MCD_E_NOTFOUND;
     if (c->serving_uses(ph)) return c->fail(MCD_E_BUSY, "phantom has queued or admitted requests");
     PhantomRec& p = c->phantoms[ph];
-    (void)hipSetDevice(c->device);
+    mcd::DeviceGuard dg(c->device);
     (void)hipDeviceSynchronize();
     c->release(p.vox, (size_t)p.nv * sizeof(uint2));
     c->release(p.maj, kNE * sizeof(float));

@@ -613,7 +613,7 @@ int mcd_simulate(mcd_ctx* c, int32_t phantom, const mcd_source* src, uint64_t n_
         return c->fail(MCD_E_INVAL, "an uncertainty needs at least 2 histories");
     const int kernel = opts ? opts->kernel : MCD_KERNEL_REGROUPED;
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
-    (void)hipSetDevice(c->device);
+    mcd::DeviceGuard dg(c->device);
     if (kernel == MCD_KERNEL_PLAIN)
         return c->simulate_plain(phantom, src, n_histories, seed, request_key, opts, out, s);
     if (kernel != MCD_KERNEL_REGROUPED) return c->fail(MCD_E_INVAL, "opts: unknown kernel");
@@ -670,7 +670,7 @@ int mcd_simulate_batch(mcd_ctx* c, int32_t phantom, const mcd_batch_item* items,
             return c->fail(MCD_E_INVAL, "an uncertainty needs at least 2 histories");
     }
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
-    (void)hipSetDevice(c->device);
+    mcd::DeviceGuard dg(c->device);
     RegroupPlan plan;
     int rc = c->plan_regroup(phantom, srcs.data(), ns.data(), keys.data(), n_items, seed, opts, false, plan);
     if (rc) return rc;

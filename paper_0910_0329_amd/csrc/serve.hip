@@ -495,7 +495,7 @@ static int submit(mcd_ctx* c, int32_t phantom, const mcd_source* src, uint64_t n
     std::lock_guard<std::mutex> g(S->mu);
     if (S->stop) return c->fail(MCD_E_INVAL, "context is shutting down");
     if (!S->running) {
-        (void)hipSetDevice(c->device);
+        mcd::DeviceGuard dg(c->device);
         if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess)
             return c->fail(MCD_E_DEVICE, "serving stream");
         try {
@@ -598,7 +598,7 @@ int mcd_wait(mcd_ctx* c, uint64_t ticket, mcd_result* out, int64_t timeout_ms)
     int rc = r->status;
     if (r->state == MCD_DONE && out) {
         const hipMemcpyKind k = out->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-        (void)hipSetDevice(c->device);
+        mcd::DeviceGuard dg(c->device);
         hipError_t e = hipSuccess;
         if (out->dose) e = hipMemcpy(out->dose, r->dose, r->out_bytes, k);
         if (e == hipSuccess && out->sigma) e = hipMemcpy(out->sigma, r->sigma, r->out_bytes, k);
