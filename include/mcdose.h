@@ -220,10 +220,15 @@ int mcd_destroy(mcd_ctx* ctx);
 int mcd_load_materials(mcd_ctx* ctx, const void* blob, size_t nbytes, int32_t* out_tables);
 int mcd_unload_materials(mcd_ctx* ctx, int32_t tables);
 
-/* Uploads a voxel phantom (material index per voxel, u8, < number of
- * materials; density per voxel, f32 > 0; both host arrays of nx*ny*nz) bound
- * to a table set, and builds its Woodcock majorant.  The phantom stays
- * resident until unloaded.  *out_phantom receives a handle. */
+/* Uploads a voxel phantom (the slab phantoms of Sec. 3 are voxel grids of
+ * materials and densities; the Woodcock tracking of Sec. 2.1 needs the
+ * majorant attenuation over them): material index per voxel, u8, < number of
+ * materials; density per voxel, f32 > 0; both host arrays of nx*ny*nz, read
+ * during the call.  The phantom is bound to a table set and its Woodcock
+ * majorant is built (max over materials present of rho mu(E), rounded up to
+ * FP32).  It stays resident until unloaded.  *out_phantom receives a handle.
+ * Errors: MCD_E_INVAL (grid sizes or spacings, material index out of range,
+ * density not finite and > 0), MCD_E_NOTFOUND (tables), MCD_E_NOMEM. */
 int mcd_load_phantom(mcd_ctx* ctx, const mcd_grid* grid, const uint8_t* mat, const float* rho,
                      int32_t tables, int32_t* out_phantom);
 int mcd_unload_phantom(mcd_ctx* ctx, int32_t phantom);
@@ -255,7 +260,8 @@ typedef struct {
 } mcd_batch_item;
 
 /* Runs many sources with uneven history counts on one phantom in one
- * regrouped launch sequence (one hipGraph launch when opts->use_graph):
+ * regrouped launch sequence (one hipGraph launch when opts->use_graph), in
+ * place of the batch-by-batch kernel relaunches of Sec. 2.2:
  * their histories share the photon and electron phases, each item keeps its
  * own tally.  Every item's result equals what mcd_simulate returns for it
  * alone with the same seed and request key (up to FP64 summation order).
