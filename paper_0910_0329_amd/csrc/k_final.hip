@@ -96,7 +96,16 @@ hipError_t launch_finalize(const double* S, const double* Q, const uint2* vox, i
 // S = sum_b T_b; the per-history variance is estimated from the spread of the
 // group means m_b = T_b / nb[b] around m = S / N,
 //     s^2 = sum_b nb[b] (m_b - m)^2 / (B' - 1),   sigma_mean^2 = s^2 / N,
-// with B' the number of non-empty groups.
+// with B' the number of non-empty groups.  The square root of that unbiased
+// variance reads low by c4(B') (normal group means: the weighted sum of
+// squares is chi-square with B' - 1 degrees of freedom), so the reported
+// sigma is sigma_mean / c4(B'), c4(k) = sqrt(2/(k-1)) Gamma(k/2) / Gamma((k-1)/2).
+DEV_INLINE double c4_of(int k)
+{
+    if (k < 2) return 1.0;
+    return sqrt(2.0 / (double)(k - 1)) * exp(lgamma(0.5 * (double)k) - lgamma(0.5 * (double)(k - 1)));
+}
+
 template <class T>
 __global__ void k_dose_batches(const FinalReq* reqs, const uint2* vox, int64_t nv, double vol)
 {
@@ -108,6 +117,7 @@ __global__ void k_dose_batches(const FinalReq* reqs, const uint2* vox, int64_t n
         N += r.nb[b];
         nz += r.nb[b] > 0.0;
     }
+    const double inv_c4 = 1.0 / c4_of(nz);
     double mx = 0.0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
          v += (int64_t)gridDim.x * blockDim.x) {
@@ -132,7 +142,7 @@ __global__ void k_dose_batches(const FinalReq* reqs, const uint2* vox, int64_t n
         const double d = m * scale;
         if (r.S) r.S[v] = S;
         if (r.dose) r.dose[v] = d;
-        if (r.sigma) r.sigma[v] = sqrt(var) * scale;
+        if (r.sigma) r.sigma[v] = sqrt(var) * inv_c4 * scale;
         if (rho >= kTissueRhoMin) mx = fmax(mx, d);
     }
     block_max_to(mx, r.red);
