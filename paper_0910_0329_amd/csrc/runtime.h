@@ -247,7 +247,7 @@ struct mcd_ctx {
     int plan_regroup(int32_t phantom, const mcd_source* const* srcs, const uint64_t* ns,
                      const uint32_t* keys, int n_req, uint64_t seed, const mcd_opts* opts,
                      bool keep_tally, mcd::RegroupPlan& plan, const mcd::ReqExtra* extra = nullptr);
-    int enqueue_regroup(const mcd::RegroupPlan& plan, bool clear_tally, hipStream_t s);
+    int enqueue_regroup(const mcd::RegroupPlan& plan, bool clear_tally, bool captured, hipStream_t s);
     int enqueue_cycles(const mcd::RegroupPlan& plan, int c0, int c1, hipStream_t s);
     int finish_regroup(mcd::RegroupPlan& plan, hipStream_t s, int* cycles_run);
     int collect_regroup(const mcd::RegroupPlan& plan, mcd_result* const* outs, mcd_result* total,

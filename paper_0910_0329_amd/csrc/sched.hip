@@ -416,27 +416,31 @@ int mcd_ctx::enqueue_cycles(const RegroupPlan& plan, int c0, int c1, hipStream_t
 
 // Clears the run state, then schedules every cycle and the finalisation.
 // Safe to capture in a graph: fills are kernels, copies happen beforehand.
-int mcd_ctx::enqueue_regroup(const RegroupPlan& plan, bool clear_tally, hipStream_t s)
+// Under capture (`captured`) no timing event is recorded (an event recorded
+// into a graph does not time its replays; the caller times the launch) and the
+// history records are not cleared (their buffer changes from call to call, so
+// the caller clears them before each launch).
+int mcd_ctx::enqueue_regroup(const RegroupPlan& plan, bool clear_tally, bool captured, hipStream_t s)
 {
     const PhantomRec& ph = phantoms[plan.phantom];
-    hipError_t e = hipEventRecord(ev[0], s);
+    hipError_t e = captured ? hipSuccess : hipEventRecord(ev[0], s);
     if (e == hipSuccess && clear_tally)
         e = launch_fill_u32(rb.tally, (size_t)plan.n_req * kBatches * ph.nv * (plan.fp32 ? 1 : 2), 0u, s);
     if (e == hipSuccess) e = launch_fill_u32(rb.ctl, 4 * sizeof(QCtl) / 4, 0u, s);
     if (e == hipSuccess) e = launch_fill_u32(rb.claim, (size_t)rb.claim_cap, 0u, s);
     if (e == hipSuccess) e = launch_fill_u32(small, kSmallBytes / 4, 0u, s);
     if (e == hipSuccess) e = launch_fill_u32(rb.red, (size_t)plan.n_req * 6, 0u, s);
-    if (e == hipSuccess && plan.req[0].hist)
+    if (e == hipSuccess && plan.req[0].hist && !captured)
         e = launch_fill_u32(plan.req[0].hist, (size_t)plan.req[0].n * 8, 0u, s);
-    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess && !captured) e = hipEventRecord(ev[1], s);
     if (e != hipSuccess) return hip_fail(e, "regrouped set-up");
     int rc = enqueue_cycles(plan, 0, plan.cycles, s);
     if (rc) return rc;
-    e = hipEventRecord(ev[2], s);
+    e = captured ? hipSuccess : hipEventRecord(ev[2], s);
     if (e == hipSuccess)
         e = launch_finalize_batches(rb.fin, plan.n_fin, ph.vox, ph.nv, ph.g.dx * ph.g.dy * ph.g.dz,
                                     plan.fp32, s);
-    if (e == hipSuccess) e = hipEventRecord(ev[3], s);
+    if (e == hipSuccess && !captured) e = hipEventRecord(ev[3], s);
     if (e != hipSuccess) return hip_fail(e, "finalisation launch");
     return MCD_OK;
 }
@@ -541,7 +545,7 @@ int mcd::run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_g
     if (e != hipSuccess) return c->hip_fail(e, "request table upload");
     int rc;
     if (!use_graph) {
-        if ((rc = c->enqueue_regroup(plan, clear_tally, s))) return rc;
+        if ((rc = c->enqueue_regroup(plan, clear_tally, false, s))) return rc;
     } else {
         // key: the launch configuration and every device pointer the graph bakes in
         std::vector<unsigned char> key;
@@ -571,7 +575,7 @@ int mcd::run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_g
             c->release_graph();
             e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return c->hip_fail(e, "graph capture");
-            rc = c->enqueue_regroup(plan, clear_tally, s);
+            rc = c->enqueue_regroup(plan, clear_tally, true, s);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(s, &g);
             if (rc) {
@@ -587,7 +591,15 @@ int mcd::run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_g
             c->graph = g;
             c->graph_key = key;
         }
-        e = hipGraphLaunch(c->graph_exec, s);
+        // the replay is timed as a whole: set-up fills, transport and
+        // finalisation (the fills and the finaliser take microseconds)
+        e = hipEventRecord(c->ev[0], s);
+        if (e == hipSuccess && plan.req[0].hist)
+            e = launch_fill_u32(plan.req[0].hist, (size_t)plan.req[0].n * 8, 0u, s);
+        if (e == hipSuccess) e = hipEventRecord(c->ev[1], s);
+        if (e == hipSuccess) e = hipGraphLaunch(c->graph_exec, s);
+        if (e == hipSuccess) e = hipEventRecord(c->ev[2], s);
+        if (e == hipSuccess) e = hipEventRecord(c->ev[3], s);
         if (e != hipSuccess) return c->hip_fail(e, "graph launch");
     }
     int cycles_run = 0;
