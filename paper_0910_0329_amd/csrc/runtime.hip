@@ -494,7 +494,7 @@ int mcd_unload_phantom(mcd_ctx* c, int32_t ph)
     std::lock_guard<mcd::FairMutex> run(c->run_mu);
     std::lock_guard<std::mutex> g(c->mu);
     if (ph < 0 || ph >= (int32_t)c->phantoms.size() || !c->phantoms[ph].live) return MCD_E_NOTFOUND;
-    if (c->serving_uses(ph)) return c->fail(MCD_E_BUSY, "phantom has queued or admitted requests");
+    if (c->serving_uses(ph)) return c->fail(MCD_E_BUSY, "phantom has requests that are not collected yet");
     PhantomRec& p = c->phantoms[ph];
     mcd::DeviceGuard dg(c->device);
     (void)hipDeviceSynchronize();

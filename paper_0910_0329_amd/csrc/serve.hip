@@ -464,8 +464,8 @@ int mcd_serve_configure(mcd_ctx* c, const mcd_serve_config* cfg)
     mcd_server* S = server_of(c);
     if (!S) return c->fail(MCD_E_NOMEM, "server state");
     std::lock_guard<std::mutex> g(S->mu);
-    if (!S->pending.empty() || !S->active.empty())
-        return c->fail(MCD_E_BUSY, "requests are queued or admitted");
+    if (!S->reqs.empty())
+        return c->fail(MCD_E_BUSY, "submitted requests are not all collected");
     S->cfg = *cfg;
     return MCD_OK;
 }
@@ -635,12 +635,10 @@ bool mcd_ctx::serving_uses(int32_t phantom)
 {
     if (!server) return false;
     std::lock_guard<std::mutex> g(server->mu);
-    for (auto& kv : server->reqs) {
-        const Request* r = kv.second.get();
-        if (r->phantom == phantom && (r->state == MCD_QUEUED || r->state == MCD_ADMITTED ||
-                                      r->state == MCD_RUNNING))
-            return true;
-    }
+    // every request on the phantom counts until mcd_wait collects it, so that
+    // whether an unload is refused does not depend on how far the device got
+    for (auto& kv : server->reqs)
+        if (kv.second->phantom == phantom) return true;
     return false;
 }
 

@@ -249,7 +249,17 @@ def test_unload_busy_and_bad_tickets(eng, pool):
     g6 = g6mv(ph, 4.0)
     eng.serve_configure(epoch_histories=50000, regroup=2)
     log("case serve unload while busy")
-    t = eng.submit(pid, g6, 20_000_000, 5, 0)
+    # an uncollected ticket keeps its phantom and the configuration busy, in
+    # any state: the refusals below do not depend on the device's progress
+    t = eng.submit(pid, g6, 2_000_000, 5, 0)
+    with pytest.raises(McdError) as ei:
+        eng.unload_phantom(pid)
+    assert ei.value.status == E_BUSY
+    with pytest.raises(McdError) as ei:
+        eng.serve_configure(epoch_histories=1000)
+    assert ei.value.status == E_BUSY
+    while eng.poll(t)[0] not in (3, 4, 5):          # DONE, FAILED, CANCELED
+        time.sleep(0.005)
     with pytest.raises(McdError) as ei:
         eng.unload_phantom(pid)
     assert ei.value.status == E_BUSY
