@@ -11,8 +11,9 @@
   sub-tallies span 2.5e9 entries, past 2^31; its dose and histories match
   the oracle's, as the plain kernel's do.
 - The CT-like 256x256x160 random-field phantom (0.2 cm voxels), 6 MV: FP32
-  against FP64 sub-tally accumulators at 1e8 histories, and the dose of
-  histories [0, 4e5) against the oracle's, per voxel class (material).
+  against FP64 sub-tally accumulators at 1e8 histories, and histories
+  [0, 4e5) against the oracle's, record by record and per voxel class
+  (material).
 """
 import sys
 
@@ -87,14 +88,14 @@ def sampled_history_parity(eng, blob, th, w):
 
 def test_headline_workload_sampled_histories(eng, blob, th):
     same, total = sampled_history_parity(eng, blob, th, configs.photon_6mv_wbw(10_000_000))
-    assert same >= 0.95 * total
+    assert same >= 0.98 * total      # measured 1997 of 2000
 
 
 def test_electron_workload_sampled_histories(eng, blob, th):
     same, total = sampled_history_parity(eng, blob, th, configs.electron_20mev_wlw(10_000_000))
     # an electron history takes hundreds of FP32 steps, so more of them part
     # from the FP64 oracle's by rounding than photon histories do (97% match)
-    assert same >= 0.9 * total
+    assert same >= 0.95 * total      # measured 1945 of 2000
 
 
 def test_large_phantom_tally_index_beyond_2_31(eng, blob, th):
@@ -126,7 +127,7 @@ def test_large_phantom_tally_index_beyond_2_31(eng, blob, th):
             r = ref["hist"]
             same = (rec["hash"] == r["hash"]) & np.isclose(rec["edep"], r["edep"], rtol=1e-3, atol=1e-6)
             log(f"    history match fraction {same.mean():.4f}")
-            assert same.mean() > 0.95
+            assert same.mean() > 0.975     # measured 0.9922
             d = g["dose"].cpu().numpy()
             s = g["sigma"].cpu().numpy()
             del g
@@ -172,24 +173,43 @@ def test_ct_phantom_fp32_against_fp64_tally(eng, ct):
 
 
 def test_ct_phantom_against_oracle_per_class(eng, blob, ct):
+    """Histories [0, 4e5) of the CT-like phantom against the oracle, with both
+    tally precisions: every history's record (event hash and deposited
+    energy); per voxel class, every voxel above 10% of Dmax within the dose
+    tolerance, and the share of those voxels whose dose differs from the
+    oracle's by less than half a standard deviation (the two runs share their
+    random numbers, so only the few histories that part ways after an FP32
+    near-tie move a voxel's dose)."""
+    import torch
     w, pid = ct
     n = 400_000
     log(f"case {w.name} n={n} against the oracle")
-    ref = oracle.simulate(blob, w.phantom, w.source, n, w.seed)
-    d_ref, s_ref, dmax_ref, _ = oracle.finalize(w.phantom, ref["S"], ref["Q"], n)
+    ref = oracle.simulate(blob, w.phantom, w.source, n, w.seed, history=True, groups=True)
+    d_ref, s_ref, dmax_ref, _ = oracle.finalize_groups(w.phantom, ref["Sb"], ref["nb"])
     mat = w.phantom.mat.reshape(-1)
     for tally_fp32 in (0, 1):
-        g = eng.simulate(pid, w.source, n, w.seed, n_vox=w.phantom.n_vox, tally_fp32=tally_fp32)
+        hist = torch.zeros(n * 4, dtype=torch.float64, device="cuda")
+        g = eng.simulate(pid, w.source, n, w.seed, n_vox=w.phantom.n_vox, tally_fp32=tally_fp32,
+                         history_records=hist)
+        rec = np.frombuffer(hist.cpu().numpy().tobytes(), dtype=oracle.HISTORY_DTYPE)
+        del hist
+        r = ref["hist"]
+        same = (rec["hash"] == r["hash"]) & np.isclose(rec["edep"], r["edep"], rtol=1e-3, atol=1e-6)
+        log(f"  fp32={tally_fp32} history match fraction {same.mean():.4f}")
+        assert same.mean() > 0.98
         d = g["dose"].cpu().numpy()
         s = g["sigma"].cpu().numpy()
         sel = d_ref > 0.1 * dmax_ref
         diff = np.abs(d - d_ref)
         ok = (diff <= 0.01 * dmax_ref) | (diff <= 2 * np.sqrt(s ** 2 + s_ref ** 2))
+        close = diff < 0.5 * s
         for name, m in CLASSES.items():
             c = sel & (mat == m)
             if c.sum() == 0:
                 continue
             log(f"  fp32={tally_fp32} {name}: {c.sum()} voxels above 10% Dmax, within tolerance "
-                f"{ok[c].mean():.4f}, max |D - D_oracle| / Dmax {diff[c].max() / dmax_ref:.2e}")
+                f"{ok[c].mean():.4f}, within 0.5 sigma {close[c].mean():.4f}, "
+                f"max |D - D_oracle| / Dmax {diff[c].max() / dmax_ref:.2e}")
             assert ok[c].all()
+            assert close[c].mean() > 0.9
         assert g["bal"]["E_src"] == pytest.approx(ref["bal"]["E_src"], rel=1e-6)

@@ -3,8 +3,12 @@ the two runs follow the same histories up to FP32 rounding).
 
 Tolerance: every voxel whose oracle dose exceeds 10% of Dmax agrees within
 1% of Dmax or within 2 combined standard deviations; the GPU energy balance
-closes to 1e-6 relative.  Diagnostic: the fraction of histories whose event
-sequence hash and deposited energy match the oracle's.
+closes to 1e-6 relative.  The fraction of histories whose event sequence
+hash and deposited energy match the oracle's is gated per case at its
+measured value less 0.015-0.025 (the FP32 transport parts ways with the FP64
+oracle after near-ties, most often in small voxels and at high electron
+energy; the cases are deterministic, so a fault that changes a few per cent
+of histories fails the gate).
 
 Both kernels are checked: the plain per-history kernel (history-by-history
 uncertainty, compared with the oracle's) and the regrouped kernel (group
@@ -114,7 +118,7 @@ def test_e20_wlw_matches_oracle(eng, blob, th, kernel):
     check_balance(g, ref)
     f = match_fraction(g, ref)
     log(f"  history match fraction {f:.4f}")
-    assert f > 0.8
+    assert f > 0.95                   # measured 0.9736
     for k in ("segments", "hinges", "moller", "brems", "compton", "spawns"):
         assert g["cnt"][k] == pytest.approx(ref["cnt"][k], rel=0.02), k
 
@@ -129,12 +133,13 @@ def test_g6mv_wbw_matches_oracle(eng, blob, th, kernel):
     check_balance(g, ref)
     f = match_fraction(g, ref)
     log(f"  history match fraction {f:.4f}")
-    assert f > 0.9
+    assert f > 0.98                   # measured 0.9989
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-@pytest.mark.parametrize("particle,e", [(POSITRON, 8.0), (PHOTON, 18.0), (ELECTRON, 0.35)])
-def test_random_field_phantom_all_particles(eng, blob, th, particle, e, kernel):
+@pytest.mark.parametrize("particle,e,gate", [(POSITRON, 8.0, 0.96), (PHOTON, 18.0, 0.975),
+                                             (ELECTRON, 0.35, 0.985)])   # measured 0.9844, 0.9937, 0.9996
+def test_random_field_phantom_all_particles(eng, blob, th, particle, e, gate, kernel):
     """Heterogeneous phantom with all four materials, ragged history count."""
     ph = phantoms.random_field_phantom(40, 0.25, seed=52, nz=48)
     x, y = ph.centre_xy()
@@ -146,12 +151,13 @@ def test_random_field_phantom_all_particles(eng, blob, th, particle, e, kernel):
     check_balance(g, ref)
     f = match_fraction(g, ref)
     log(f"  history match fraction {f:.4f}")
-    assert f > 0.8
+    assert f > gate
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-@pytest.mark.parametrize("particle,middle,n", [(ELECTRON, "lung", 4_000), (PHOTON, "bone", 60_000)])
-def test_paper_geometry(eng, blob, th, particle, middle, n, kernel):
+@pytest.mark.parametrize("particle,middle,n,gate", [(ELECTRON, "lung", 4_000, 0.88),
+                                                    (PHOTON, "bone", 60_000, 0.98)])   # measured 0.9025, 0.9983
+def test_paper_geometry(eng, blob, th, particle, middle, n, gate, kernel):
     """The paper's benchmark geometry (Sec. 3): 61x61x150 voxels of 0.5x0.5x0.2 cm,
     5/5/20 cm slabs, point source at SSD 90 cm with the 10x10 cm field at SAD 100."""
     w = configs.paper_workload(particle, middle, n)
@@ -161,7 +167,7 @@ def test_paper_geometry(eng, blob, th, particle, middle, n, kernel):
     check_balance(g, ref)
     f = match_fraction(g, ref)
     log(f"  history match fraction {f:.4f}")
-    assert f > 0.8
+    assert f > gate
 
 
 @pytest.fixture(scope="module")
@@ -172,8 +178,9 @@ def angular(eng):
 
 
 @pytest.mark.parametrize("kernel", ("plain", "regrouped"))
-@pytest.mark.parametrize("particle,e,n", [(PHOTON, 18.0, 6_000), (ELECTRON, 15.0, 3_000), (PHOTON, 0.6, 40_000)])
-def test_angular_tables_match_oracle(eng, angular, particle, e, n, kernel):
+@pytest.mark.parametrize("particle,e,n,gate", [(PHOTON, 18.0, 6_000, 0.975), (ELECTRON, 15.0, 3_000, 0.925),
+                                               (PHOTON, 0.6, 40_000, 0.99)])   # measured 0.9930, 0.9457, 1.0
+def test_angular_tables_match_oracle(eng, angular, particle, e, n, gate, kernel):
     """Tables with the angular flag: photoelectrons at Sauter angles,
     bremsstrahlung photons and pair leptons at forward-peaked angles."""
     blob, tha = angular
@@ -186,7 +193,7 @@ def test_angular_tables_match_oracle(eng, angular, particle, e, n, kernel):
     check_balance(g, ref)
     f = match_fraction(g, ref)
     log(f"  history match fraction {f:.4f}")
-    assert f > 0.8
+    assert f > gate
     assert g["cnt"]["photo"] + g["cnt"]["pair"] + g["cnt"]["brems"] > 0
 
 
@@ -204,13 +211,13 @@ def test_density_effect_tables_match_oracle(eng, kernel):
     check_balance(g, ref)
     f = match_fraction(g, ref)
     log(f"  history match fraction {f:.4f}")
-    assert f > 0.8
+    assert f > 0.945                  # measured 0.9657
     eng.unload_materials(thd)
 
 
 @pytest.mark.parametrize("kernel", ("plain", "regrouped"))
-@pytest.mark.parametrize("middle", ("lung", "bone"))
-def test_per_element_screening_tables_match_oracle(eng, kernel, middle):
+@pytest.mark.parametrize("middle,gate", [("lung", 0.88), ("bone", 0.925)])   # measured 0.9040, 0.9450
+def test_per_element_screening_tables_match_oracle(eng, kernel, middle, gate):
     """Tables whose elastic cross sections screen each element by its own
     charge: the same transport code on different 1/lambda1 (hinge spacing)
     and 1/lambda2, 20 MeV electrons on the paper's slab phantoms."""
@@ -224,16 +231,16 @@ def test_per_element_screening_tables_match_oracle(eng, kernel, middle):
     check_balance(g, ref)
     f = match_fraction(g, ref)
     log(f"  history match fraction {f:.4f}")
-    assert f > 0.8
+    assert f > gate
     assert g["cnt"]["hinges"] == pytest.approx(ref["cnt"]["hinges"], rel=0.02)
     eng.unload_materials(the)
 
 
 @pytest.mark.parametrize("kernel", ("plain", "regrouped"))
-@pytest.mark.parametrize("variant,particle,e,n", [("rayleigh", PHOTON, 0.15, 60_000),
-                                                  ("refined", PHOTON, 0.25, 60_000),
-                                                  ("refined", PHOTON, 6.0, 30_000)])
-def test_rayleigh_tables_match_oracle(eng, variant, particle, e, n, kernel):
+@pytest.mark.parametrize("variant,particle,e,n,gate", [("rayleigh", PHOTON, 0.15, 60_000, 0.99),
+                                                       ("refined", PHOTON, 0.25, 60_000, 0.99),
+                                                       ("refined", PHOTON, 6.0, 30_000, 0.98)])
+def test_rayleigh_tables_match_oracle(eng, variant, particle, e, n, gate, kernel):
     """Tables with the Rayleigh flag (alone, and with emission angles and the
     density effect): coherent scattering as a fourth photon interaction."""
     from paper_0910_0329_amd.inputs import tables
@@ -250,17 +257,17 @@ def test_rayleigh_tables_match_oracle(eng, variant, particle, e, n, kernel):
     f = match_fraction(g, ref)
     nr, nr_ref = g["cnt"]["rayleigh"], ref["cnt"]["rayleigh"]
     log(f"  history match fraction {f:.4f}; Rayleigh events {nr} (oracle {nr_ref})")
-    assert f > 0.8
+    assert f > gate                   # measured 1.0, 1.0, 0.9978
     assert nr_ref > (200 if e < 1.0 else 5)
     assert abs(nr - nr_ref) <= 0.05 * nr_ref + 10
 
 
 @pytest.mark.parametrize("kernel", ("plain", "regrouped"))
-@pytest.mark.parametrize("variant,particle,e,n", [("hinge2", ELECTRON, 12.0, 4_000),
-                                                  ("hinge2", PHOTON, 8.0, 30_000),
-                                                  ("refined", ELECTRON, 18.0, 3_000),
-                                                  ("hinge2 r=1.8", ELECTRON, 12.0, 4_000)])
-def test_second_moment_hinge_tables_match_oracle(eng, variant, particle, e, n, kernel):
+@pytest.mark.parametrize("variant,particle,e,n,gate", [("hinge2", ELECTRON, 12.0, 4_000, 0.935),
+                                                       ("hinge2", PHOTON, 8.0, 30_000, 0.98),
+                                                       ("refined", ELECTRON, 18.0, 3_000, 0.905),
+                                                       ("hinge2 r=1.8", ELECTRON, 12.0, 4_000, 0.94)])
+def test_second_moment_hinge_tables_match_oracle(eng, variant, particle, e, n, gate, kernel):
     """Tables with the hinge2 flag: hinge angles from the law matching both
     Lewis moments (the device interpolates its per-node parameters, the
     oracle solves for them at the hinge energy).  "r=1.8" sets
@@ -284,16 +291,16 @@ def test_second_moment_hinge_tables_match_oracle(eng, variant, particle, e, n, k
     check_balance(g, ref)
     f = match_fraction(g, ref)
     log(f"  history match fraction {f:.4f}; hinges {g['cnt']['hinges']} (oracle {ref['cnt']['hinges']})")
-    assert f > 0.8
+    assert f > gate                   # measured 0.9543, 0.9965, 0.9253, 0.9607
     assert g["cnt"]["hinges"] == pytest.approx(ref["cnt"]["hinges"], rel=0.02)
 
 
 @pytest.mark.parametrize("kernel", ("plain", "regrouped", "queued"))
-@pytest.mark.parametrize("variant,particle,e,n", [("bhabha", POSITRON, 12.0, 4_000),
-                                                  ("bhabha", POSITRON, 0.9, 20_000),
-                                                  ("refined", POSITRON, 6.0, 4_000),
-                                                  ("bhabha", PHOTON, 18.0, 8_000)])
-def test_bhabha_tables_match_oracle(eng, variant, particle, e, n, kernel):
+@pytest.mark.parametrize("variant,particle,e,n,gate", [("bhabha", POSITRON, 12.0, 4_000, 0.94),
+                                                       ("bhabha", POSITRON, 0.9, 20_000, 0.985),
+                                                       ("refined", POSITRON, 6.0, 4_000, 0.965),
+                                                       ("bhabha", PHOTON, 18.0, 8_000, 0.975)])
+def test_bhabha_tables_match_oracle(eng, variant, particle, e, n, gate, kernel):
     """Tables with the Bhabha flag: positrons take their own range and
     stopping power and hard Bhabha events (read from the global positron
     table); electrons are unchanged.  Photons at 18 MeV reach positrons by
@@ -312,7 +319,7 @@ def test_bhabha_tables_match_oracle(eng, variant, particle, e, n, kernel):
     f = match_fraction(g, ref)
     nb, nb_ref = g["cnt"]["bhabha"], ref["cnt"]["bhabha"]
     log(f"  history match fraction {f:.4f}; Bhabha events {nb} (oracle {nb_ref})")
-    assert f > 0.8
+    assert f > gate                   # measured 0.9610, 0.9989, 0.9840, 0.9935
     assert nb_ref > 20
     assert abs(nb - nb_ref) <= 0.05 * nb_ref + 10
     assert g["cnt"]["moller"] == pytest.approx(ref["cnt"]["moller"], rel=0.05, abs=10)
@@ -443,7 +450,7 @@ def test_single_voxel_phantom(eng, blob, th, kernel, particle):
     assert g["bal"]["E_esc"] > 0.5 * g["bal"]["E_src"]
     f = match_fraction(g, ref)
     log(f"  history match fraction {f:.4f}")
-    assert f > 0.9
+    assert f > 0.99                   # measured 1.0 (photons), 0.9998 (electrons)
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
@@ -486,7 +493,7 @@ def test_field_wider_than_the_phantom(eng, blob, th, kernel):
     assert g["bal"]["E_miss"] == pytest.approx(ref["bal"]["E_miss"], rel=1e-4)
     f = match_fraction(g, ref)
     log(f"  history match fraction {f:.4f}")
-    assert f > 0.95
+    assert f > 0.99                   # measured 1.0
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
@@ -514,7 +521,7 @@ def test_top_of_the_history_range(eng, blob, th, kernel):
     check_balance(g, ref)
     f = match_fraction(g, ref)
     log(f"  history match fraction {f:.4f}")
-    assert f > 0.9
+    assert f > 0.98                   # measured 0.9988
 
 
 def test_batch_equals_separate_runs(eng, th):
@@ -545,6 +552,44 @@ def test_batch_equals_separate_runs(eng, th):
             assert r["dmax"] == pytest.approx(alone["dmax"], rel=1e-9)
         esum += alone["bal"]["E_src"]
     assert tot["bal"]["E_src"] == pytest.approx(esum, rel=1e-9)
+    eng.unload_phantom(pid)
+
+
+def test_graph_replays_with_new_history_records(eng, th):
+    """A replayed graph uses the history-record buffer of its own call: two
+    graph calls with different buffers (the second pre-filled with garbage)
+    both give the records of the call without a graph, and the first buffer
+    is not touched by the second call.  The replay's kernel time is a time
+    of the replay (at most the call's wall time)."""
+    import time
+
+    import torch
+    w = configs.electron_20mev_wlw(3_000)
+    pid = eng.load_phantom(w.phantom, th)
+    nv, n = w.phantom.n_vox, w.n_histories
+    log("case graph history records")
+
+    def records(buf):
+        return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=oracle.HISTORY_DTYPE)
+
+    plain = torch.zeros(n * 4, dtype=torch.float64, device="cuda")
+    ref = eng.simulate(pid, w.source, n, w.seed, n_vox=nv, history_records=plain)
+    a = torch.zeros(n * 4, dtype=torch.float64, device="cuda")
+    eng.simulate(pid, w.source, n, w.seed, n_vox=nv, history_records=a, use_graph=1)
+    rec_a = records(a).copy()
+    b = torch.full((n * 4,), 7.0, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = eng.simulate(pid, w.source, n, w.seed, n_vox=nv, history_records=b, use_graph=1)
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    want = records(plain)
+    for got in (rec_a, records(b)):
+        np.testing.assert_array_equal(got["hash"], want["hash"])
+        np.testing.assert_array_equal(got["n_particles"], want["n_particles"])
+        np.testing.assert_allclose(got["edep"], want["edep"], rtol=1e-9, atol=1e-12)
+    np.testing.assert_array_equal(records(a), rec_a)
+    np.testing.assert_allclose(g["dose"].cpu().numpy(), ref["dose"].cpu().numpy(), rtol=1e-9, atol=1e-25)
+    assert 0 < g["kernel_ms"] <= wall_ms
     eng.unload_phantom(pid)
 
 
