@@ -119,6 +119,8 @@ struct RegroupPlan {
     bool refined_build = false;      // force the kernels built with the refinement code
     bool use_queues = false;
     Sched sched{};
+    RegroupBufs* bufs = nullptr;     // device buffers the run uses (the context's, or a
+    unsigned char* small = nullptr;  // carve-out of the no-allocation scratch)
     std::vector<ReqDev> req;
     std::vector<FinalReq> fin;
     std::vector<double> nb;          // n_req * kBatches histories per sub-tally
@@ -244,6 +246,9 @@ struct mcd_ctx {
     int simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n, uint64_t seed,
                        uint32_t key, const mcd_opts* opts, mcd_result* out, hipStream_t s);
     // regrouped engine
+    int prepare_regroup(int32_t phantom, const mcd_source* const* srcs, const uint64_t* ns,
+                        const uint32_t* keys, int n_req, uint64_t seed, const mcd_opts* opts,
+                        mcd::RegroupPlan& plan, const mcd::ReqExtra* extra = nullptr);
     int plan_regroup(int32_t phantom, const mcd_source* const* srcs, const uint64_t* ns,
                      const uint32_t* keys, int n_req, uint64_t seed, const mcd_opts* opts,
                      bool keep_tally, mcd::RegroupPlan& plan, const mcd::ReqExtra* extra = nullptr);

@@ -221,9 +221,12 @@ static double batch_count(uint64_t first, uint64_t n, int b)
     return (double)(upto(first + n) - upto(first));
 }
 
-int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const uint64_t* ns,
-                          const uint32_t* keys, int n_req, uint64_t seed, const mcd_opts* opts,
-                          bool keep_tally, RegroupPlan& plan, const ReqExtra* extra)
+// Validates the requests and options of a regrouped run and fills the plan's
+// host side (request and finaliser tables, launch shape, schedule); touches no
+// device memory.
+int mcd_ctx::prepare_regroup(int32_t phantom, const mcd_source* const* srcs, const uint64_t* ns,
+                             const uint32_t* keys, int n_req, uint64_t seed, const mcd_opts* opts,
+                             RegroupPlan& plan, const ReqExtra* extra)
 {
     const PhantomRec& ph = phantoms[phantom];
     if (n_req < 1 || n_req > kMaxBatch) return fail(MCD_E_INVAL, "1 to 4096 requests per launch");
@@ -287,6 +290,19 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
     // the electron phase of the last cycle keeps its photons on the lane stacks,
     // so no cycle is needed after the last new history
     plan.cycles = (int)((plan.total + plan.chunk - 1) / plan.chunk);
+    return MCD_OK;
+}
+
+int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const uint64_t* ns,
+                          const uint32_t* keys, int n_req, uint64_t seed, const mcd_opts* opts,
+                          bool keep_tally, RegroupPlan& plan, const ReqExtra* extra)
+{
+    int rc = prepare_regroup(phantom, srcs, ns, keys, n_req, seed, opts, plan, extra);
+    if (rc) return rc;
+    const PhantomRec& ph = phantoms[phantom];
+    const uint64_t lanes = (uint64_t)plan.blocks * plan.threads;
+    plan.bufs = &rb;
+    plan.small = small;
 
     // device buffers
     const size_t elem = plan.fp32 ? sizeof(float) : sizeof(double);
@@ -362,32 +378,33 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
 int mcd_ctx::enqueue_cycles(const RegroupPlan& plan, int c0, int c1, hipStream_t s)
 {
     const PhantomRec& ph = phantoms[plan.phantom];
+    const RegroupBufs& B = *plan.bufs;
     KPhase k;
     std::memset(&k, 0, sizeof k);
     fill_geom(k.g, ph);
     if (plan.refined_build) k.g.t.refined = 1;
-    k.req = rb.req;
+    k.req = B.req;
     k.n_req = plan.n_req;
     k.tally_fp32 = plan.fp32;
     k.total = plan.total;
     k.chunk = plan.chunk;
-    k.claim = rb.claim;
-    k.q_cap = rb.cap;
+    k.claim = B.claim;
+    k.q_cap = B.cap;
     k.use_queues = plan.use_queues;
     k.nv = ph.nv;
-    k.bal = (double*)(small + kOffBal);
-    k.cnt = (unsigned long long*)(small + kOffCnt);
-    k.err = (int*)(small + kOffErr);
-    k.scratch = rb.scratch;
+    k.bal = (double*)(plan.small + kOffBal);
+    k.cnt = (unsigned long long*)(plan.small + kOffCnt);
+    k.err = (int*)(plan.small + kOffErr);
+    k.scratch = B.scratch;
     k.stack_depth = plan.depth;
     k.lane_bytes = phase_lane_bytes(plan.depth);
     k.sched = plan.sched;
-    char* Qg[2] = {rb.queues, rb.queues + (size_t)rb.cap * kRec};
-    char* Qe[2] = {rb.queues + (size_t)2 * rb.cap * kRec, rb.queues + (size_t)3 * rb.cap * kRec};
-    QCtl* Cg[2] = {rb.ctl + 0, rb.ctl + 1};
-    QCtl* Ce[2] = {rb.ctl + 2, rb.ctl + 3};
+    char* Qg[2] = {B.queues, B.queues + (size_t)B.cap * kRec};
+    char* Qe[2] = {B.queues + (size_t)2 * B.cap * kRec, B.queues + (size_t)3 * B.cap * kRec};
+    QCtl* Cg[2] = {B.ctl + 0, B.ctl + 1};
+    QCtl* Ce[2] = {B.ctl + 2, B.ctl + 3};
     for (int c = c0; c < c1; ++c) {
-        if (c >= rb.claim_cap) return fail(MCD_E_OVERFLOW, "too many transport cycles");
+        if (c >= B.claim_cap) return fail(MCD_E_OVERFLOW, "too many transport cycles");
         const int a = c & 1, b = (c + 1) & 1;
         k.cycle = (uint32_t)c;
         // photon phase: photons of the previous electron phase and new histories
@@ -423,13 +440,14 @@ int mcd_ctx::enqueue_cycles(const RegroupPlan& plan, int c0, int c1, hipStream_t
 int mcd_ctx::enqueue_regroup(const RegroupPlan& plan, bool clear_tally, bool captured, hipStream_t s)
 {
     const PhantomRec& ph = phantoms[plan.phantom];
+    const RegroupBufs& B = *plan.bufs;
     hipError_t e = captured ? hipSuccess : hipEventRecord(ev[0], s);
     if (e == hipSuccess && clear_tally)
-        e = launch_fill_u32(rb.tally, (size_t)plan.n_req * kBatches * ph.nv * (plan.fp32 ? 1 : 2), 0u, s);
-    if (e == hipSuccess) e = launch_fill_u32(rb.ctl, 4 * sizeof(QCtl) / 4, 0u, s);
-    if (e == hipSuccess) e = launch_fill_u32(rb.claim, (size_t)rb.claim_cap, 0u, s);
-    if (e == hipSuccess) e = launch_fill_u32(small, kSmallBytes / 4, 0u, s);
-    if (e == hipSuccess) e = launch_fill_u32(rb.red, (size_t)plan.n_req * 6, 0u, s);
+        e = launch_fill_u32(B.tally, (size_t)plan.n_req * kBatches * ph.nv * (plan.fp32 ? 1 : 2), 0u, s);
+    if (e == hipSuccess) e = launch_fill_u32(B.ctl, 4 * sizeof(QCtl) / 4, 0u, s);
+    if (e == hipSuccess) e = launch_fill_u32(B.claim, (size_t)B.claim_cap, 0u, s);
+    if (e == hipSuccess) e = launch_fill_u32(plan.small, kSmallBytes / 4, 0u, s);
+    if (e == hipSuccess) e = launch_fill_u32(B.red, (size_t)plan.n_req * 6, 0u, s);
     if (e == hipSuccess && plan.req[0].hist && !captured)
         e = launch_fill_u32(plan.req[0].hist, (size_t)plan.req[0].n * 8, 0u, s);
     if (e == hipSuccess && !captured) e = hipEventRecord(ev[1], s);
@@ -438,7 +456,7 @@ int mcd_ctx::enqueue_regroup(const RegroupPlan& plan, bool clear_tally, bool cap
     if (rc) return rc;
     e = captured ? hipSuccess : hipEventRecord(ev[2], s);
     if (e == hipSuccess)
-        e = launch_finalize_batches(rb.fin, plan.n_fin, ph.vox, ph.nv, ph.g.dx * ph.g.dy * ph.g.dz,
+        e = launch_finalize_batches(B.fin, plan.n_fin, ph.vox, ph.nv, ph.g.dx * ph.g.dy * ph.g.dz,
                                     plan.fp32, s);
     if (e == hipSuccess && !captured) e = hipEventRecord(ev[3], s);
     if (e != hipSuccess) return hip_fail(e, "finalisation launch");
@@ -451,12 +469,13 @@ int mcd_ctx::enqueue_regroup(const RegroupPlan& plan, bool clear_tally, bool cap
 int mcd_ctx::finish_regroup(RegroupPlan& plan, hipStream_t s, int* cycles_run)
 {
     const PhantomRec& ph = phantoms[plan.phantom];
+    const RegroupBufs& B = *plan.bufs;
     int done = plan.cycles;
     for (;;) {
         QCtl ctl[4];
         int err = 0;
-        hipError_t e = hipMemcpyAsync(ctl, rb.ctl, sizeof ctl, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(&err, small + kOffErr, 4, hipMemcpyDeviceToHost, s);
+        hipError_t e = hipMemcpyAsync(ctl, B.ctl, sizeof ctl, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&err, plan.small + kOffErr, 4, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "regrouped run");
         if (err)
@@ -466,10 +485,10 @@ int mcd_ctx::finish_regroup(RegroupPlan& plan, hipStream_t s, int* cycles_run)
         int rc = enqueue_cycles(plan, done, done + 1, s);
         if (rc) return rc;
         done += 1;
-        e = launch_fill_u32(rb.red, (size_t)plan.n_req * 6, 0u, s);
+        e = launch_fill_u32(B.red, (size_t)plan.n_req * 6, 0u, s);
         if (e == hipSuccess) e = hipEventRecord(ev[2], s);
         if (e == hipSuccess)
-            e = launch_finalize_batches(rb.fin, plan.n_fin, ph.vox, ph.nv,
+            e = launch_finalize_batches(B.fin, plan.n_fin, ph.vox, ph.nv,
                                         ph.g.dx * ph.g.dy * ph.g.dz, plan.fp32, s);
         if (e == hipSuccess) e = hipEventRecord(ev[3], s);
         if (e != hipSuccess) return hip_fail(e, "extra cycles");
@@ -482,18 +501,20 @@ int mcd_ctx::collect_regroup(const RegroupPlan& plan, mcd_result* const* outs, m
                              hipStream_t s)
 {
     const PhantomRec& ph = phantoms[plan.phantom];
+    const RegroupBufs& B = *plan.bufs;
     const size_t vb = (size_t)ph.nv * sizeof(double);
     unsigned char host_small[kSmallBytes];
     std::vector<double> red((size_t)plan.n_req * 3);
-    hipError_t e = hipMemcpyAsync(host_small, small, kSmallBytes, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(host_small, plan.small, kSmallBytes, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(red.data(), rb.red, red.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(red.data(), B.red, red.size() * sizeof(double), hipMemcpyDeviceToHost, s);
     for (int r = 0; r < plan.n_req && e == hipSuccess; ++r) {
         mcd_result* o = outs[r];
         if (!o) continue;
         const hipMemcpyKind k = o->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-        if (o->dose) e = hipMemcpyAsync(o->dose, plan.fin[r].dose, vb, k, s);
-        if (e == hipSuccess && o->sigma) e = hipMemcpyAsync(o->sigma, plan.fin[r].sigma, vb, k, s);
+        if (o->dose && o->dose != plan.fin[r].dose) e = hipMemcpyAsync(o->dose, plan.fin[r].dose, vb, k, s);
+        if (e == hipSuccess && o->sigma && o->sigma != plan.fin[r].sigma)
+            e = hipMemcpyAsync(o->sigma, plan.fin[r].sigma, vb, k, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "result copy");
@@ -539,9 +560,9 @@ void mcd_ctx::release_graph()
 int mcd::run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_graph, hipStream_t s)
 {
     // S outputs are written by the finaliser straight from the sub-tallies
-    hipError_t e = hipMemcpy(c->rb.req, plan.req.data(), plan.n_req * sizeof(ReqDev), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(plan.bufs->req, plan.req.data(), plan.n_req * sizeof(ReqDev), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(c->rb.fin, plan.fin.data(), plan.n_req * sizeof(FinalReq), hipMemcpyHostToDevice);
+        e = hipMemcpy(plan.bufs->fin, plan.fin.data(), plan.n_req * sizeof(FinalReq), hipMemcpyHostToDevice);
     if (e != hipSuccess) return c->hip_fail(e, "request table upload");
     int rc;
     if (!use_graph) {
