@@ -231,6 +231,9 @@ int mcd_unload_materials(mcd_ctx* ctx, int32_t tables);
  * density not finite and > 0), MCD_E_NOTFOUND (tables), MCD_E_NOMEM. */
 int mcd_load_phantom(mcd_ctx* ctx, const mcd_grid* grid, const uint8_t* mat, const float* rho,
                      int32_t tables, int32_t* out_phantom);
+/* Frees a phantom.  MCD_E_BUSY while served requests on it are not all
+ * collected by mcd_wait (whatever their state), MCD_E_NOTFOUND for an unknown
+ * handle.  Waits for the device run in progress. */
 int mcd_unload_phantom(mcd_ctx* ctx, int32_t phantom);
 
 /* Transports n_histories source histories through a phantom and returns the
@@ -317,9 +320,9 @@ typedef struct {
     uint64_t counters[MCD_NCOUNT];       /* filled when opts.diagnostics */
 } mcd_serve_stats;
 
-/* Sets the serving configuration.  Allowed while no request is queued or
- * admitted (before the first submit, or once all are collected); else
- * MCD_E_BUSY.  NULL restores the defaults. */
+/* Sets the serving configuration.  Allowed before the first submit or once
+ * every submitted request is collected by mcd_wait; else MCD_E_BUSY.  NULL
+ * restores the defaults. */
 int mcd_serve_configure(mcd_ctx* ctx, const mcd_serve_config* cfg);
 
 /* Queues a request (2 <= n_histories < 2^32, seed < 2^32) and returns its
@@ -363,6 +366,52 @@ int mcd_wait(mcd_ctx* ctx, uint64_t ticket, mcd_result* out, int64_t timeout_ms)
 int mcd_cancel(mcd_ctx* ctx, uint64_t ticket);
 
 int mcd_serve_stats_get(mcd_ctx* ctx, mcd_serve_stats* out);
+
+/* ------------------------------------------------------------ verification
+ *
+ * These calls run the device functions of the transport kernels on caller
+ * data, so that a test can hold them against independent implementations:
+ * the Philox4x32-10 generator that replaces the paper's RANECU streams
+ * (Sec. 2.4), and the lookups in the FP32 cross-section tables that the
+ * paper keeps in texture memory (Sec. 2.3) and this engine stages into LDS.
+ * Both are blocking; every pointer is a device pointer on the context's
+ * device, owned by the caller. */
+
+/* Philox4x32-10 (Salmon et al., SC'11) under the key (seed, key) applied to
+ * n_blocks counters of four u32 words each (counters[4 i .. 4 i + 3] = c0..c3);
+ * the four output words of block i go to out[4 i .. 4 i + 3].  Both arrays
+ * 16-byte aligned; 1 <= n_blocks <= 2^32.  MCD_E_INVAL otherwise. */
+int mcd_check_philox(mcd_ctx* ctx, uint32_t seed, uint32_t key, const uint32_t* counters,
+                     uint64_t n_blocks, uint32_t* out, void* hip_stream);
+
+/* Table quantities (per mass, as in the table blob; the values are those
+ * indices of the blob's quantity list), the phantom's Woodcock majorant
+ * (1/cm), and the inverse of the CSDA range (electron or positron: x is a
+ * range in g/cm^2 and the result an energy in MeV). */
+enum {
+    MCD_Q_MU_C = 0, MCD_Q_MU_PE = 1, MCD_Q_MU_PP = 2, MCD_Q_RANGE = 3, MCD_Q_LAMBDA1_INV = 4,
+    MCD_Q_SIGMA_M = 5, MCD_Q_SIGMA_B = 6, MCD_Q_MU_R = 8, MCD_Q_RANGE_POS = 10, MCD_Q_SIGMA_BH = 11,
+    MCD_Q_MAJORANT = 100, MCD_Q_RANGE_INV = 101, MCD_Q_RANGE_POS_INV = 102
+};
+
+/* Evaluates `quantity` of `material` (ignored for the majorant) at n points
+ * x (energies in MeV, or ranges for the inverses) with the tables of
+ * `phantom` as the transport kernels do: FP32 nodes staged in LDS,
+ * interpolation linear in log E (clamped to the grid), range inversion on
+ * the same interpolant.  1 <= n <= 2^32.  MCD_E_NOTFOUND for an unknown
+ * phantom, MCD_E_INVAL for a bad material, quantity or size. */
+int mcd_check_tables(mcd_ctx* ctx, int32_t phantom, int32_t material, int32_t quantity, const float* x,
+                     uint64_t n, float* out, void* hip_stream);
+
+/* Measurement of the ceiling of the tally's operation (the dose collection by
+ * atomic floating-point addition of Sec. 2.4, here FP64): adds 1.0 at
+ * target[idx[i]] for i < n, reps times over, with the same atomic
+ * instruction the tally flushes use, and returns the device time in *ms
+ * (host).  target (n_target doubles) and idx (n u32) are device arrays of the
+ * caller; indices >= n_target are skipped.  The rate for an address stream
+ * drawn like the tally's flushes bounds how fast a kernel can flush. */
+int mcd_measure_atomics(mcd_ctx* ctx, double* target, uint64_t n_target, const uint32_t* idx, uint64_t n,
+                        int32_t reps, double* ms, void* hip_stream);
 
 /* Status and error text.  mcd_last_error reports the last failure of a call
  * made on this context by the calling thread. */

@@ -6,6 +6,7 @@ this module.  It loads `liboracle.so` built from `oracle.c` by `make -C oracle`.
 from __future__ import annotations
 
 import ctypes as C
+import multiprocessing
 import os
 import subprocess
 from concurrent.futures import ProcessPoolExecutor
@@ -68,6 +69,9 @@ def lib():
         L.orc_interp.argtypes = [vp, sz, C.c_int, C.c_int, C.c_double, dp]
         L.orc_range_inverse.argtypes = [vp, sz, C.c_int, C.c_double, dp]
         L.orc_majorant.argtypes = [vp, sz, C.POINTER(Grid), u8p, f32p, dp]
+        L.orc_philox_n.argtypes = [C.c_uint32, C.c_uint32, vp, sz, vp]
+        L.orc_interp_n.argtypes = [vp, sz, C.c_int, C.c_int, dp, sz, dp]
+        L.orc_range_inverse_n.argtypes = [vp, sz, C.c_int, C.c_int, dp, sz, dp]
         L.orc_simulate.argtypes = [vp, sz, C.POINTER(Grid), u8p, f32p, C.POINTER(Source),
                                    C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, dp, dp, dp,
                                    C.POINTER(C.c_uint64), vp, vp]
@@ -134,6 +138,30 @@ def range_inverse(blob: bytes, m: int, r: float) -> float:
     return out.value
 
 
+def philox_n(k0: int, k1: int, ctr: np.ndarray) -> np.ndarray:
+    """Philox4x32-10 of an (n, 4) uint32 array of counters."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    out = np.empty_like(c)
+    lib().orc_philox_n(k0, k1, c.ctypes.data, c.shape[0], out.ctypes.data)
+    return out
+
+
+def interp_n(blob: bytes, m: int, q: int, e) -> np.ndarray:
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    out = np.empty_like(e)
+    if lib().orc_interp_n(blob, len(blob), m, q, _dp(e), e.size, _dp(out)):
+        raise ValueError("orc_interp_n rejected its input")
+    return out
+
+
+def range_inverse_n(blob: bytes, m: int, q: int, r) -> np.ndarray:
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    out = np.empty_like(r)
+    if lib().orc_range_inverse_n(blob, len(blob), m, q, _dp(r), r.size, _dp(out)):
+        raise ValueError("orc_range_inverse_n rejected its input")
+    return out
+
+
 def _phantom_arrays(ph):
     mat = np.ascontiguousarray(ph.mat, dtype=np.uint8)
     rho = np.ascontiguousarray(ph.rho, dtype=np.float32)
@@ -182,9 +210,11 @@ def simulate(blob: bytes, ph, src, n: int, seed: int, key: int = 0, first: int =
 
 
 def _sim_chunk(args):
+    import time
     blob, ph, src, first, n, seed, key = args
+    t0 = time.perf_counter()
     r = simulate(blob, ph, src, n, seed, key, first=first)
-    return r["S"], r["Q"], r["bal_raw"], r["cnt_raw"]
+    return r["S"], r["Q"], r["bal_raw"], r["cnt_raw"], time.perf_counter() - t0
 
 
 def simulate_parallel(blob, ph, src, n, seed, key=0, first=0, procs=None) -> dict:
@@ -197,8 +227,12 @@ def simulate_parallel(blob, ph, src, n, seed, key=0, first=0, procs=None) -> dic
     Q = np.zeros(ph.n_vox)
     bal = np.zeros(NBAL)
     cnt = np.zeros(NCOUNT, dtype=np.uint64)
-    with ProcessPoolExecutor(len(jobs)) as ex:
-        for s_, q_, b_, c_ in ex.map(_sim_chunk, jobs):
+    busy = 0.0
+    # fresh interpreters, not forks: a caller that has opened a GPU keeps its
+    # device handles to itself
+    with ProcessPoolExecutor(len(jobs), mp_context=multiprocessing.get_context("spawn")) as ex:
+        for s_, q_, b_, c_, t_ in ex.map(_sim_chunk, jobs):
+            busy += t_
             S += s_
             Q += q_
             bal += b_
@@ -207,7 +241,7 @@ def simulate_parallel(blob, ph, src, n, seed, key=0, first=0, procs=None) -> dic
             cnt[25:] += c_[25:]
     return {"S": S, "Q": Q, "bal": dict(zip(BAL_NAMES, bal)), "bal_raw": bal,
             "cnt": dict(zip(COUNT_NAMES, (int(x) for x in cnt))), "cnt_raw": cnt, "n": n,
-            "procs": len(jobs)}
+            "procs": len(jobs), "busy_s": busy}
 
 
 def first_interaction(blob, ph, src, n, seed, key=0, kinds=False):

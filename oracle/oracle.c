@@ -195,6 +195,38 @@ int orc_range_inverse(const void* blob, size_t nbytes, int m, double r, double* 
     return rc;
 }
 
+void orc_philox_n(uint32_t k0, uint32_t k1, const uint32_t* ctr, size_t n, uint32_t* out)
+{
+    for (size_t i = 0; i < n; ++i) orc_philox(k0, k1, ctr + 4 * i, out + 4 * i);
+}
+
+int orc_interp_n(const void* blob, size_t nbytes, int m, int q, const double* e, size_t n, double* out)
+{
+    tables t;
+    if (load_tables(blob, nbytes, &t)) return -1;
+    int rc = -1;
+    if (m >= 0 && m < t.n_mat && q >= 0 && q < NQ) {
+        for (size_t i = 0; i < n; ++i) out[i] = interp(&t, tab(&t, m, q), e[i]);
+        rc = 0;
+    }
+    free(t.q);
+    return rc;
+}
+
+int orc_range_inverse_n(const void* blob, size_t nbytes, int m, int q, const double* r, size_t n,
+                        double* out)
+{
+    tables t;
+    if (load_tables(blob, nbytes, &t)) return -1;
+    int rc = -1;
+    if (m >= 0 && m < t.n_mat && (q == Q_R || q == Q_RP)) {
+        for (size_t i = 0; i < n; ++i) out[i] = range_inverse(&t, tab(&t, m, q), r[i]);
+        rc = 0;
+    }
+    free(t.q);
+    return rc;
+}
+
 /* ---------------------------------------------------------------- geometry */
 
 typedef struct {

@@ -80,6 +80,14 @@ int orc_interp(const void* blob, size_t nbytes, int m, int q, double e, double* 
 /* Inverse of the interpolated range of material m: T with R(T) = r. */
 int orc_range_inverse(const void* blob, size_t nbytes, int m, double r, double* out);
 
+/* Array forms of the three functions above, for tests that compare many
+ * points: n counters (4 words each, out likewise); n energies; n ranges, with
+ * q the range quantity to invert (3: electron range R, 10: positron range). */
+void orc_philox_n(uint32_t k0, uint32_t k1, const uint32_t* ctr, size_t n, uint32_t* out);
+int orc_interp_n(const void* blob, size_t nbytes, int m, int q, const double* e, size_t n, double* out);
+int orc_range_inverse_n(const void* blob, size_t nbytes, int m, int q, const double* r, size_t n,
+                        double* out);
+
 /* Majorant attenuation mu_max(E_i) (1/cm) at the 512 grid nodes. */
 int orc_majorant(const void* blob, size_t nbytes, const orc_grid* g, const uint8_t* mat,
                  const float* rho, double* out512);

@@ -13,7 +13,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmcdose.so")
-SOURCES = ("k_plain.hip", "k_regroup.hip", "k_final.hip", "runtime.hip", "sched.hip", "serve.hip")
+SOURCES = ("k_plain.hip", "k_regroup.hip", "k_final.hip", "k_check.hip", "runtime.hip", "sched.hip",
+           "serve.hip")
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",

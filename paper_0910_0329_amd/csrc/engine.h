@@ -165,5 +165,6 @@ hipError_t launch_fill_u32(void* p, size_t n_words, uint32_t v, hipStream_t s);
 hipError_t init_kernels(int max_lds);
 hipError_t init_plain_kernels(int max_lds);
 hipError_t init_phase_kernels(int max_lds);
+hipError_t init_check_kernels(int max_lds);
 
 }  // namespace mcd

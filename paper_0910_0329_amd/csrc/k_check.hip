@@ -1,0 +1,177 @@
+// Verification entry points: the device functions the transport kernels use
+// for random numbers (Philox4x32-10) and table lookups (interpolation in the
+// FP32 tables staged in LDS, the Woodcock majorant, range inversion), run on
+// caller data so that tests can hold them against independent FP64 and
+// integer implementations.  They share the transport's code, not a copy of it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+
+#include "mcdose.h"
+#include "runtime.h"
+#include "transport.h"
+
+namespace mcd {
+
+// A transport lane with no particles: only its table and geometry helpers run.
+struct CheckLane : Transport<CheckLane, false, true> {
+    DEV explicit CheckLane(const KGeom& g) : Transport<CheckLane, false, true>(g) {}
+    DEV void deposit(const Part&, int, float) {}
+    DEV void spawn(const Part&) {}
+    DEV void flush_particle(const Part&) {}
+    DEV void add_track(const Part&, float) {}
+    DEV void escaped(const Part&) {}
+    DEV void particle_done(const Part&, uint64_t) {}
+    DEV bool fetch(Part&) { return false; }
+};
+
+__global__ __launch_bounds__(256) void k_check_philox(uint32_t k0, uint32_t k1, const uint4* ctr,
+                                                      uint64_t n, uint4* out)
+{
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        uint4 c = ctr[t];
+        philox10(k0, k1, c.x, c.y, c.z, c.w);
+        out[t] = c;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_check_tables(KGeom g, int m, int q, const float* x,
+                                                      uint64_t n, float* out)
+{
+    extern __shared__ float4 lds[];
+    Env env;
+    float* extra;
+    stage_tables(g, lds, env, &extra);
+    __syncthreads();
+    CheckLane L(g);
+    L.env = env;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const float v = x[t];
+        float r = 0.f;
+        if (q == MCD_Q_RANGE_INV || q == MCD_Q_RANGE_POS_INV) {
+            r = L.range_inverse(m, v, kNE - 2, q == MCD_Q_RANGE_POS_INV);
+        } else {
+            int i;
+            float fr;
+            L.eidx(v, i, fr);
+            const int k = m * kNE + i;
+            switch (q) {
+            case MCD_Q_MU_C: r = lerp(env.phot[k].x, env.phot[k + 1].x, fr); break;
+            case MCD_Q_MU_PE: r = lerp(env.phot[k].y, env.phot[k + 1].y, fr); break;
+            case MCD_Q_MU_PP: r = lerp(env.phot[k].z, env.phot[k + 1].z, fr); break;
+            case MCD_Q_MU_R: r = lerp(env.phot[k].w, env.phot[k + 1].w, fr); break;
+            case MCD_Q_RANGE: r = lerp(env.elec[k].x, env.elec[k + 1].x, fr); break;
+            case MCD_Q_LAMBDA1_INV: r = lerp(env.elec[k].y, env.elec[k + 1].y, fr); break;
+            case MCD_Q_SIGMA_M: r = lerp(env.elec[k].z, env.elec[k + 1].z, fr); break;
+            case MCD_Q_SIGMA_B: r = lerp(env.elec[k].w, env.elec[k + 1].w, fr); break;
+            case MCD_Q_RANGE_POS: r = lerp(g.t.posi[k].x, g.t.posi[k + 1].x, fr); break;
+            case MCD_Q_SIGMA_BH: r = lerp(g.t.posi[k].y, g.t.posi[k + 1].y, fr); break;
+            case MCD_Q_MAJORANT: r = lerp(env.maj[i], env.maj[i + 1], fr); break;
+            default: break;
+            }
+        }
+        out[t] = r;
+    }
+}
+
+// FP64 atomic adds of 1.0 at target[idx[i]], i < n, `reps` times over the
+// stream: the tally's own operation, on a caller-chosen address stream.
+// Indices past the target are skipped.
+__global__ __launch_bounds__(256) void k_atomic_stream(double* target, uint64_t n_target, const uint32_t* idx,
+                                                       uint64_t n, int reps)
+{
+    for (int r = 0; r < reps; ++r)
+        for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+             t += (uint64_t)gridDim.x * blockDim.x) {
+            const uint32_t j = idx[t];
+            if (j < n_target) unsafeAtomicAdd(target + j, 1.0);
+        }
+}
+
+hipError_t init_check_kernels(int max_lds)
+{
+    return hipFuncSetAttribute((const void*)k_check_tables, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+}
+
+static int check_blocks(uint64_t n)
+{
+    const uint64_t b = (n + 255) / 256;
+    return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+}  // namespace mcd
+
+using namespace mcd;
+
+int mcd_check_philox(mcd_ctx* c, uint32_t seed, uint32_t key, const uint32_t* counters, uint64_t n_blocks,
+                     uint32_t* out, void* hip_stream)
+{
+    if (!c) return MCD_E_INVAL;
+    if (!counters || !out || n_blocks == 0 || n_blocks > ((uint64_t)1 << 32))
+        return c->fail(MCD_E_INVAL, "check_philox: need device counters and outputs, 1 <= n <= 2^32");
+    if (((uintptr_t)counters | (uintptr_t)out) & 15u)
+        return c->fail(MCD_E_INVAL, "check_philox: counters and out must be 16-byte aligned");
+    mcd::DeviceGuard dg(c->device);
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    hipLaunchKernelGGL(k_check_philox, dim3(check_blocks(n_blocks)), dim3(256), 0, s, seed, key,
+                       (const uint4*)counters, n_blocks, (uint4*)out);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? MCD_OK : c->hip_fail(e, "check_philox");
+}
+
+int mcd_check_tables(mcd_ctx* c, int32_t phantom, int32_t material, int32_t quantity, const float* x,
+                     uint64_t n, float* out, void* hip_stream)
+{
+    if (!c) return MCD_E_INVAL;
+    std::lock_guard<mcd::FairMutex> run_lock(c->run_mu);
+    if (phantom < 0 || phantom >= (int32_t)c->phantoms.size() || !c->phantoms[phantom].live)
+        return c->fail(MCD_E_NOTFOUND, "unknown phantom handle");
+    const PhantomRec& ph = c->phantoms[phantom];
+    const int n_mat = c->tables[ph.tables].n_mat;
+    if (!x || !out || n == 0 || n > ((uint64_t)1 << 32))
+        return c->fail(MCD_E_INVAL, "check_tables: need device inputs and outputs, 1 <= n <= 2^32");
+    if (material < 0 || material >= n_mat) return c->fail(MCD_E_INVAL, "check_tables: material out of range");
+    const bool known = (quantity >= MCD_Q_MU_C && quantity <= MCD_Q_SIGMA_B) || quantity == MCD_Q_MU_R ||
+                       quantity == MCD_Q_RANGE_POS || quantity == MCD_Q_SIGMA_BH ||
+                       quantity == MCD_Q_MAJORANT || quantity == MCD_Q_RANGE_INV ||
+                       quantity == MCD_Q_RANGE_POS_INV;
+    if (!known) return c->fail(MCD_E_INVAL, "check_tables: unknown quantity");
+    KGeom g;
+    c->fill_geom(g, ph);
+    mcd::DeviceGuard dg(c->device);
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    hipLaunchKernelGGL(k_check_tables, dim3(check_blocks(n)), dim3(256), transport_lds_bytes(n_mat), s, g,
+                       material, quantity, x, n, out);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? MCD_OK : c->hip_fail(e, "check_tables");
+}
+
+int mcd_measure_atomics(mcd_ctx* c, double* target, uint64_t n_target, const uint32_t* idx, uint64_t n,
+                        int32_t reps, double* ms, void* hip_stream)
+{
+    if (!c) return MCD_E_INVAL;
+    if (!target || !idx || !ms || n_target == 0 || n == 0 || n > ((uint64_t)1 << 32) || reps < 1 ||
+        reps > 1000)
+        return c->fail(MCD_E_INVAL, "measure_atomics: need device target and indices, 1 <= n <= 2^32, "
+                                    "1 <= reps <= 1000");
+    mcd::DeviceGuard dg(c->device);
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    const int blocks = (int)std::min<uint64_t>((n + 255) / 256, (uint64_t)c->cu_count * 32);
+    hipError_t e = hipEventRecord(c->ev[0], s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_atomic_stream, dim3(blocks), dim3(256), 0, s, target, n_target, idx, n, reps);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->ev[1], s);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ev[1]);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, c->ev[0], c->ev[1]);
+    if (e != hipSuccess) return c->hip_fail(e, "measure_atomics");
+    *ms = t;
+    return MCD_OK;
+}

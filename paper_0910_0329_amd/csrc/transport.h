@@ -37,6 +37,10 @@ enum { EV_VIRTUAL = 1, EV_COMPTON, EV_PHOTO, EV_PAIR, EV_PAIR_VOID, EV_G_ESCAPE,
 
 DEV float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
+// Linear interpolation between two table nodes (fr in [0, 1)); every table
+// lookup of the transport goes through it.
+DEV float lerp(float a, float b, float fr) { return a + (b - a) * fr; }
+
 // Wave-aggregated counter increment: the active lanes that reach it share one
 // atomic add of their count on *ctr; each gets old + (its rank among them).
 DEV unsigned int wave_fetch_add(unsigned int* ctr)
@@ -549,7 +553,7 @@ struct Transport {
         int i;
         float fr;
         eidx(q.e, i, fr);
-        const float mu_max = env.maj[i] + (env.maj[i + 1] - env.maj[i]) * fr;
+        const float mu_max = lerp(env.maj[i], env.maj[i + 1], fr);
         const float s = fdiv(neg_ln(uni_ready(q)), mu_max);   // prefetch left >= 2 words
         count(MCD_C_FLIGHTS);
         q.x += s * q.u;
@@ -570,10 +574,10 @@ struct Transport {
         const float rho = __uint_as_float(vd.x);
         const int m = (int)vd.y;
         const float4 a = env.phot[m * kNE + i], b = env.phot[m * kNE + i + 1];
-        const float mu_c = rho * (a.x + (b.x - a.x) * fr);
-        const float mu_pe = rho * (a.y + (b.y - a.y) * fr);
-        const float mu_pp = rho * (a.z + (b.z - a.z) * fr);
-        const float mu_r = REF ? rho * (a.w + (b.w - a.w) * fr) : 0.f;
+        const float mu_c = rho * lerp(a.x, b.x, fr);
+        const float mu_pe = rho * lerp(a.y, b.y, fr);
+        const float mu_pp = rho * lerp(a.z, b.z, fr);
+        const float mu_r = REF ? rho * lerp(a.w, b.w, fr) : 0.f;
         const float xs = uni_ready(q) * mu_max;
         if (xs < mu_c) {
             ev(EV_COMPTON);
@@ -713,16 +717,16 @@ struct Transport {
         float fr;
         node(xt, i, fr);
         const float4 a = env.elec[m * kNE + i], b = env.elec[m * kNE + i + 1];
-        float rt = a.x + (b.x - a.x) * fr;
-        const float lam = a.y + (b.y - a.y) * fr;
-        float s_inel = a.z + (b.z - a.z) * fr;
+        float rt = lerp(a.x, b.x, fr);
+        const float lam = lerp(a.y, b.y, fr);
+        float s_inel = lerp(a.z, b.z, fr);
         const bool pos = own_positron(q);
         if (pos) {
             const float2 p0 = g.t.posi[m * kNE + i], p1 = g.t.posi[m * kNE + i + 1];
-            rt = p0.x + (p1.x - p0.x) * fr;
-            s_inel = p0.y + (p1.y - p0.y) * fr;
+            rt = lerp(p0.x, p1.x, fr);
+            s_inel = lerp(p0.y, p1.y, fr);
         }
-        const float sh = s_inel + (a.w + (b.w - a.w) * fr);
+        const float sh = s_inel + lerp(a.w, b.w, fr);
         // the five limits, ties resolved in the order E, h, kappa, b, f
         float l = fmaxf(0.f, (rt - (pos ? env.r_abs_pos[m] : env.r_abs[m])) * irho);
         int lim = LIM_E;
@@ -883,12 +887,12 @@ struct Transport {
         float fr;
         eidx(T, i, fr);
         const float4 a = env.elec[m * kNE + i], b = env.elec[m * kNE + i + 1];
-        float sm = a.z + (b.z - a.z) * fr;
-        const float sb = a.w + (b.w - a.w) * fr;
+        float sm = lerp(a.z, b.z, fr);
+        const float sb = lerp(a.w, b.w, fr);
         const bool pos = own_positron(q);
         if (pos) {
             const float2 p0 = g.t.posi[m * kNE + i], p1 = g.t.posi[m * kNE + i + 1];
-            sm = p0.y + (p1.y - p0.y) * fr;
+            sm = lerp(p0.y, p1.y, fr);
         }
         const bool inelastic = uni(q) * (sm + sb) < sm;
         if (pos && inelastic) {

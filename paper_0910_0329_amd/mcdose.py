@@ -132,6 +132,9 @@ def lib():
         L.mcd_wait.argtypes = [vp, C.c_uint64, C.POINTER(Result), C.c_int64]
         L.mcd_cancel.argtypes = [vp, C.c_uint64]
         L.mcd_serve_stats_get.argtypes = [vp, C.POINTER(ServeStats)]
+        L.mcd_measure_atomics.argtypes = [vp, vp, C.c_uint64, vp, C.c_uint64, i32, C.POINTER(C.c_double), vp]
+        L.mcd_check_philox.argtypes = [vp, C.c_uint32, C.c_uint32, vp, C.c_uint64, vp, vp]
+        L.mcd_check_tables.argtypes = [vp, i32, i32, i32, vp, C.c_uint64, vp, vp]
         L.mcd_status_string.argtypes = [C.c_int]
         L.mcd_status_string.restype = C.c_char_p
         L.mcd_last_error.argtypes = [vp]
@@ -143,7 +146,13 @@ def lib():
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_load_materials", "mcd_unload_materials",
             "mcd_load_phantom", "mcd_unload_phantom", "mcd_simulate", "mcd_simulate_batch",
             "mcd_serve_configure", "mcd_submit", "mcd_submit_adaptive", "mcd_poll", "mcd_wait", "mcd_cancel",
-            "mcd_serve_stats_get", "mcd_status_string", "mcd_last_error")
+            "mcd_serve_stats_get", "mcd_check_philox", "mcd_check_tables", "mcd_measure_atomics", "mcd_status_string",
+            "mcd_last_error")
+
+# Quantities of mcd_check_tables (include/mcdose.h).
+Q_MU_C, Q_MU_PE, Q_MU_PP, Q_RANGE, Q_LAMBDA1_INV, Q_SIGMA_M, Q_SIGMA_B = range(7)
+Q_MU_R, Q_RANGE_POS, Q_SIGMA_BH = 8, 10, 11
+Q_MAJORANT, Q_RANGE_INV, Q_RANGE_POS_INV = 100, 101, 102
 
 
 def make_source(src) -> Source:
@@ -300,6 +309,37 @@ class Engine:
             d["sigma_bar"] = r.sigma_bar
             outs.append(d)
         return outs, _scalars(tot)
+
+    # ------------------------------------------------------- verification
+
+    def check_philox(self, seed: int, key: int, counters, stream=None):
+        """Philox4x32-10 blocks of the device generator for a (n, 4) uint32
+        CUDA tensor of counters; returns a tensor of the same shape."""
+        import torch
+        ctr = counters.contiguous()
+        out = torch.empty_like(ctr)
+        self._check(lib().mcd_check_philox(self._h, seed, key, ctr.data_ptr(), ctr.shape[0], out.data_ptr(),
+                                           _stream_ptr(stream)), "mcd_check_philox")
+        return out
+
+    def check_tables(self, phantom: int, material: int, quantity: int, x, stream=None):
+        """A table quantity as the transport kernels evaluate it, at the points
+        of a float32 CUDA tensor x; returns a float32 tensor."""
+        import torch
+        xs = x.contiguous()
+        out = torch.empty_like(xs)
+        self._check(lib().mcd_check_tables(self._h, phantom, material, quantity, xs.data_ptr(), xs.numel(),
+                                           out.data_ptr(), _stream_ptr(stream)), "mcd_check_tables")
+        return out
+
+    def measure_atomics(self, target, idx, reps: int = 1, stream=None) -> float:
+        """Device milliseconds for reps x idx.numel() FP64 atomic adds at
+        target[idx] (float64 and int32/uint32 CUDA tensors)."""
+        ms = C.c_double()
+        self._check(lib().mcd_measure_atomics(self._h, target.data_ptr(), target.numel(), idx.data_ptr(),
+                                              idx.numel(), reps, C.byref(ms), _stream_ptr(stream)),
+                    "mcd_measure_atomics")
+        return ms.value
 
     # ------------------------------------------------------------ serving
 
