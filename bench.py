@@ -71,10 +71,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=2_000_000,
-                    help="photon histories of the CPU oracle sample (0: skip)")
-    ap.add_argument("--serve-seconds", type=float, default=4.0,
-                    help="arrival window of the served form (0: skip); 60 is the full stream")
+    ap.add_argument("--cpu-sample", type=int, default=250_000,
+                    help="photon histories per host process of the CPU oracle sample (0: skip); "
+                         "electrons take a tenth as many")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="arrival window of the served form (0: skip); 60 s is the full stream")
+    ap.add_argument("--serve-adaptive-seconds", type=float, default=15.0,
+                    help="arrival window of the served form with sigma-bar targets (0: skip)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline steps (used for profiling the transport phase)")
     ap.add_argument("--lockstep-probe", action="store_true",
@@ -104,6 +107,81 @@ def timed(fn, reps):
 
 def closure(b):
     return abs(b["E_csda"] + b["E_local"] + b["E_esc"] + b["E_miss"] - b["E_src"]) / b["E_src"]
+
+
+def atomic_ceilings(eng, nv, S, Q, flush_rate, flushes_per_history):
+    """FP64 atomic-add rates of the device (mcd_measure_atomics) on three
+    address streams over the 16 sub-tallies of an nv-voxel phantom."""
+    import numpy as np
+    import torch
+    n_target = 16 * nv
+    target = torch.zeros(n_target, dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(11)
+    n = 1 << 25
+    w = np.where(Q > 0, S * S / np.where(Q > 0, Q, 1.0), 0.0)
+    w = w / w.sum()
+    streams = {
+        "replay": rng.integers(0, 16, n, dtype=np.int64) * nv + rng.choice(nv, n, p=w),
+        "uniform": rng.integers(0, n_target, n, dtype=np.int64),
+        "one_address": np.full(n, n_target // 2, dtype=np.int64),
+    }
+    out = {"flushes_per_history": flushes_per_history, "flush_rate": flush_rate, "unit": "atomics/s"}
+    for name, idx in streams.items():
+        t = torch.from_numpy(idx.astype(np.uint32).view(np.int32)).cuda()
+        eng.measure_atomics(target, t, 1)
+        reps = 1 if name == "one_address" else 4
+        ms = eng.measure_atomics(target, t, reps)
+        out[f"ceiling_{name}"] = n * reps / (ms * 1e-3)
+        del t
+    out["atomic_frac"] = flush_rate / out["ceiling_replay"]
+    return out
+
+
+def cpu_leg(per_proc, blob, eng, run, wg, pg, we, pe):
+    """The FP64 oracle on the host cores: P single-threaded processes run
+    disjoint history ranges of the headline (and the 20 MeV electron)
+    workload with the same keys, merged in FP64.  The same histories on the
+    GPU (plain kernel) give the dose agreement."""
+    import numpy as np
+
+    import oracle
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    out, agree = {}, {}
+    for tag, w, p, n in (("photon", wg, pg, per_proc * procs), ("electron", we, pe, per_proc // 10 * procs)):
+        t0 = time.perf_counter()
+        ref = oracle.simulate_parallel(blob, w.phantom, w.source, n, w.seed, w.request_key, procs=procs)
+        dt = time.perf_counter() - t0
+        # value: whole job on the wall clock (process start-up included);
+        # per_core: histories per second of one process's transport time
+        out[tag] = {"value": n / dt, "per_core": n / ref["busy_s"], "histories": n, "s": dt}
+        d_ref, s_ref, dmax_ref, sbar_ref = oracle.finalize(w.phantom, ref["S"], ref["Q"], n)
+        g = run(w, p, n, kernel=1)
+        d = g["dose"].cpu().numpy()
+        diff = np.abs(d - d_ref)
+        sel = d_ref > 0.1 * dmax_ref
+        agree[w.name] = {"histories": n, "same_keys": True, "max_abs_diff_over_dmax": float(diff.max() / dmax_ref),
+                         "frac_within_1pct_dmax_above_10pct": float((diff[sel] <= 0.01 * dmax_ref).mean()),
+                         "frac_within_1pct_dmax_all": float((diff <= 0.01 * dmax_ref).mean()),
+                         "voxels_above_10pct": int(sel.sum()), "sigma_bar_oracle": sbar_ref,
+                         "sigma_bar_gpu": g["sigma_bar"]}
+    cpu = {"value": out["photon"]["value"], "unit": "histories/s", "cores": procs, "kind": "oracle",
+           "per_core": out["photon"]["per_core"], "cpu_model": model,
+           "sample": f"histories [0, {out['photon']['histories']}) of the headline workload and keys, FP64, "
+                     f"{procs} single-threaded processes on disjoint ranges, tallies merged",
+           "electron_value": out["electron"]["value"], "electron_per_core": out["electron"]["per_core"],
+           "electron_sample": f"histories [0, {out['electron']['histories']}) of the 20 MeV pencil workload, "
+                              f"{procs} processes",
+           "seconds": out["photon"]["s"] + out["electron"]["s"]}
+    return cpu, agree
 
 
 def main():
@@ -164,7 +242,7 @@ def main():
         return
 
     # ------------------------------------------------------------ headline
-    pilot = run(wg, pg, wg.n_histories, kernel=KERNEL_PLAIN)
+    pilot = run(wg, pg, wg.n_histories, kernel=KERNEL_PLAIN, want_tallies=True)
     n1 = int(math.ceil(wg.n_histories * (pilot["sigma_bar"] / 0.01) ** 2))
     log(f"photon pilot sigma-bar {pilot['sigma_bar']:.4f} -> N_1% = {n1}")
     # The N^-1/2 projection undershoots a little (Dmax falls as its noise does,
@@ -223,6 +301,21 @@ def main():
         tb = TRAFFIC_BYTES_PER_HIST.get(wg.name)
         roofline["traffic"] = tb * n1 / max(launches, 1) if tb else None
     line["roofline"] = roofline
+
+    # ------------------------------------------------------- atomic ceiling
+    # The tally flushes are FP64 atomic adds (the paper's dose collection by
+    # atomic float addition, Sec. 2.4).  Their rate in the headline step
+    # (flushes per history from a diagnostics run x histories/s) against the
+    # rate the device sustains for the same operation on address streams: the
+    # flush pattern of the headline (a voxel drawn with probability proportional
+    # to S^2/Q of the plain pilot, the number of histories that deposit in it,
+    # and a uniform sub-tally), uniform addresses over the 16 sub-tallies, and
+    # every lane on one address.
+    rd = run(wg, pg, 2_000_000, diagnostics=1, want_dose=False)
+    flushes = rd["cnt"]["flushes"] / 2_000_000
+    roofline["atomic"] = atomic_ceilings(eng, wg.phantom.n_vox, pilot["S"].cpu().numpy(),
+                                         pilot["Q"].cpu().numpy(), flushes * n1 / (k_ms * 1e-3), flushes)
+    log(f"atomics: {roofline['atomic']}")
 
     if args.headline_only:
         line["cpu_baseline"] = None
@@ -355,11 +448,26 @@ def main():
         return r
 
     ts_, _ = timed(separate, 1)
+
+    def separate_regrouped():
+        r = None
+        for s, n, k in items:
+            r = eng.simulate(pg, s, n, 4, k, n_vox=wg.phantom.n_vox)
+        return r
+
+    tsr_, _ = timed(separate_regrouped, 1)
     forms["batched"] = {"workload": "128 beamlets 0.5x0.5 cm on g6mv_wbw_61x61x60 (even 6 MV, odd e- U(6,20) MeV)",
                         "histories": n_tot, "hist_per_s": n_tot / tb_, "ms": tb_ * 1e3,
                         "kernel_ms": tot["kernel_ms"], "tuned_opts": tuned,
+                        "kernel_hist_per_s": n_tot / (tot["kernel_ms"] * 1e-3),
+                        "kernel_ms_is_replay_time": "graph replay (set-up fills, transport, finalisation) "
+                                                    "timed by events around the launch",
                         "separate_plain_hist_per_s": n_tot / ts_, "separate_plain_ms": ts_ * 1e3,
-                        "speedup_vs_separate": ts_ / tb_, "energy_balance_rel": closure(tot["bal"])}
+                        "separate_regrouped_hist_per_s": n_tot / tsr_, "separate_regrouped_ms": tsr_ * 1e3,
+                        "speedup_vs_separate": ts_ / tb_, "speedup_vs_separate_regrouped": tsr_ / tb_,
+                        "energy_balance_rel": closure(tot["bal"])}
+    if tot["kernel_ms"] > tb_ * 1e3:
+        raise SystemExit(f"batched: replay time {tot['kernel_ms']:.1f} ms exceeds the call's {tb_ * 1e3:.1f} ms")
     log(f"batched: {n_tot / tb_:.3e} hist/s vs {n_tot / ts_:.3e} separate plain")
 
     # ------------------------------------------------------------ served
@@ -379,27 +487,38 @@ def main():
         forms["served"] = sv
         log(f"served: p50 {sv['p50_ms']:.0f} ms p99 {sv['p99_ms']:.0f} ms, {sv['hist_per_s']:.3e} hist/s "
             f"(offered {sv['offered_hist_per_s']:.3e})")
-        sa = serving.replay(eng, pool_ids, pool, reqs, cal, seed=5, collectors=32, adaptive=True, log=log)
-        sa["workload"] = "the same arrivals; each request stops at its own sigma-bar target (at most 5e7 histories)"
+    if args.serve_seconds > 0 and args.serve_adaptive_seconds > 0:
+        reqs_a = configs.serving_requests(20.0, args.serve_adaptive_seconds, seed=5)
+        sa = serving.replay(eng, pool_ids, pool, reqs_a, cal, seed=5, collectors=32, adaptive=True, log=log)
+        sa["workload"] = (f"the first {args.serve_adaptive_seconds:g} s of the same arrivals; each request stops "
+                          "at its own sigma-bar target (at most 5e7 histories)")
         forms["served_adaptive"] = sa
         log(f"served adaptive: p50 {sa['p50_ms']:.0f} ms p99 {sa['p99_ms']:.0f} ms, {sa['hist_per_s']:.3e} hist/s")
     line["forms"] = forms
 
+    # ------------------------------------------------------------ end to end
+    # The paper's time T covers initialisation, transfers and finalisation
+    # (Sec. 3): here table and phantom upload, the regrouped run of N_1%
+    # histories, dose and sigma copied to host memory, and the unloads.
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th2 = eng.load_materials(blob)
+    pg2 = eng.load_phantom(wg.phantom, th2)
+    r2 = run(wg, pg2, n1, device_out=False)
+    eng.unload_phantom(pg2)
+    eng.unload_materials(th2)
+    t_e2e = time.perf_counter() - t0
+    line["end_to_end"] = {"s": t_e2e, "hist_per_s": n1 / t_e2e, "histories": n1, "sigma_bar": r2["sigma_bar"],
+                          "includes": "table blob and phantom upload, Woodcock majorant, transport, finalisation, "
+                                      "dose and sigma copied to host memory, unloads"}
+    log(f"end to end: {t_e2e:.3f} s for {n1} histories")
+
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     if args.cpu_sample > 0:
-        import oracle
-        n_cpu = args.cpu_sample
-        c0 = time.perf_counter()
-        oracle.simulate(blob, wg.phantom, wg.source, n_cpu, wg.seed, wg.request_key)
-        c1 = time.perf_counter()
-        n_cpu_e = max(1000, n_cpu // 40)
-        oracle.simulate(blob, we.phantom, we.source, n_cpu_e, we.seed, we.request_key)
-        c2 = time.perf_counter()
-        cpu = {"value": n_cpu / (c1 - c0), "unit": "histories/s", "cores": 1, "kind": "oracle",
-               "sample": f"histories [0, {n_cpu}) of the headline workload and keys, FP64, one thread",
-               "electron_value": n_cpu_e / (c2 - c1),
-               "electron_sample": f"histories [0, {n_cpu_e}) of the 20 MeV pencil workload, FP64, one thread"}
+        cpu, line["oracle_agreement"] = cpu_leg(args.cpu_sample, blob, eng, run, wg, pg, we, pe)
+        log(f"cpu baseline: {cpu}")
+        log(f"oracle agreement: {line['oracle_agreement']}")
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     eng.close()
