@@ -252,6 +252,31 @@ int mcd_simulate(mcd_ctx* ctx, int32_t phantom, const mcd_source* src, uint64_t 
                  uint64_t seed, uint32_t request_key, const mcd_opts* opts, mcd_result* out,
                  void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * regrouped run of mcd_simulate with lane stacks, calling no hipMalloc or
+ * hipFree.  Every buffer beyond the inputs and outputs (run scalars, counters,
+ * request tables, the 16 sub-tallies, the lane stacks) lives in a device array
+ * of 512 MiB that the library holds on each device it runs on until the
+ * process ends.  The run must fit in it: 16 x nv tally words (8 bytes, or 4
+ * with tally_fp32) plus grid lanes x stack_depth x 48 bytes (each lane's
+ * share rounded up to 256 bytes; stack_depth 0 means 26 here) plus a few KB;
+ * otherwise MCD_E_INVAL names the size needed.  With the default launch shape
+ * of a 256-CU device (262144 lanes, 320 MiB of stacks) that leaves room for
+ * 1.5e6 voxels with FP64 sums or 3.1e6 with FP32 sums; fewer grid_blocks or a
+ * smaller stack_depth leave more.  A particle stack that
+ * overflows ends the run with MCD_E_OVERFLOW (raise stack_depth).
+ * out->dose and out->sigma must be device buffers (out->on_device = 1); S is
+ * optional and Q is refused.  opts as for mcd_simulate, except that kernel
+ * must be MCD_KERNEL_REGROUPED, regroup 0 or 2, use_graph and accumulate 0.
+ * The histories and results equal mcd_simulate's with the same arguments, up
+ * to FP64 summation order.  Calls on one device share the array: the library
+ * runs them one at a time (calls that overlap from several threads or
+ * contexts wait for each other). */
+int mcd_simulate_noalloc(mcd_ctx* ctx, int32_t phantom, const mcd_source* src, uint64_t n_histories,
+                         uint64_t seed, uint32_t request_key, const mcd_opts* opts, mcd_result* out,
+                         void* hip_stream);
+
 /* One beam or beamlet of a batched call. */
 typedef struct {
     mcd_source src;

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmcdose.so")
 SOURCES = ("k_plain.hip", "k_regroup.hip", "k_final.hip", "k_check.hip", "runtime.hip", "sched.hip",
-           "serve.hip")
+           "serve.hip", "noalloc.hip")
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",

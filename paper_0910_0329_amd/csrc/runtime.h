@@ -137,6 +137,9 @@ namespace mcd {
 int run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_graph, hipStream_t s);
 // Records per particle queue for cycles of `chunk` new histories.
 unsigned int queue_capacity(uint64_t chunk);
+// Looks up the calling thread's current device's copy of the no-allocation
+// scratch array (once per device; later calls return the first outcome).
+hipError_t noalloc_setup(int device);
 
 // Makes `dev` the calling thread's current HIP device for the guard's scope
 // and gives the caller back its own device afterwards, so that no entry point

@@ -142,6 +142,10 @@ int mcd_create(int device, uint64_t hbm_budget_bytes, mcd_ctx** out)
         mcd_destroy(c);
         return MCD_E_DEVICE;
     }
+    // the no-allocation entry point's scratch on this device (its status is
+    // kept and reported by that entry point; the rest of the library does not
+    // depend on it)
+    (void)mcd::noalloc_setup(device);
     *out = c;
     return MCD_OK;
 }

@@ -132,6 +132,8 @@ def lib():
         L.mcd_wait.argtypes = [vp, C.c_uint64, C.POINTER(Result), C.c_int64]
         L.mcd_cancel.argtypes = [vp, C.c_uint64]
         L.mcd_serve_stats_get.argtypes = [vp, C.POINTER(ServeStats)]
+        L.mcd_simulate_noalloc.argtypes = [vp, i32, C.POINTER(Source), C.c_uint64, C.c_uint64, C.c_uint32,
+                                           C.POINTER(Opts), C.POINTER(Result), vp]
         L.mcd_measure_atomics.argtypes = [vp, vp, C.c_uint64, vp, C.c_uint64, i32, C.POINTER(C.c_double), vp]
         L.mcd_check_philox.argtypes = [vp, C.c_uint32, C.c_uint32, vp, C.c_uint64, vp, vp]
         L.mcd_check_tables.argtypes = [vp, i32, i32, i32, vp, C.c_uint64, vp, vp]
@@ -144,7 +146,7 @@ def lib():
 
 
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_load_materials", "mcd_unload_materials",
-            "mcd_load_phantom", "mcd_unload_phantom", "mcd_simulate", "mcd_simulate_batch",
+            "mcd_load_phantom", "mcd_unload_phantom", "mcd_simulate", "mcd_simulate_noalloc", "mcd_simulate_batch",
             "mcd_serve_configure", "mcd_submit", "mcd_submit_adaptive", "mcd_poll", "mcd_wait", "mcd_cancel",
             "mcd_serve_stats_get", "mcd_check_philox", "mcd_check_tables", "mcd_measure_atomics", "mcd_status_string",
             "mcd_last_error")
@@ -259,6 +261,32 @@ class Engine:
         self._check(rc, "mcd_simulate")
         out = dict(bufs)
         out.update(_scalars(r))
+        out["n"] = n
+        return out
+
+    def simulate_noalloc(self, phantom: int, src, n: int, seed: int, key: int = 0, *, dose, sigma, S=None,
+                         stream=None, history_records=None, **opts) -> dict:
+        """mcd_simulate_noalloc: the regrouped run into caller-owned device
+        tensors (float64 dose, sigma and optional S of n_vox each); the library
+        allocates nothing.  Returns the scalar results."""
+        import torch
+        s = make_source(src)
+        o = make_opts(**opts)
+        if history_records is not None:
+            o.history_records = history_records.data_ptr()
+            o.diagnostics = 1
+        r = Result()
+        r.dose = dose.data_ptr()
+        r.sigma = sigma.data_ptr()
+        if S is not None:
+            r.S = S.data_ptr()
+        r.on_device = 1
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        rc = lib().mcd_simulate_noalloc(self._h, phantom, C.byref(s), n, seed, key, C.byref(o), C.byref(r),
+                                        _stream_ptr(stream))
+        self._check(rc, "mcd_simulate_noalloc")
+        out = _scalars(r)
         out["n"] = n
         return out
 

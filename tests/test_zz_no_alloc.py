@@ -1,0 +1,87 @@
+"""mcd_simulate_noalloc against mcd_simulate: the entry point for callers that
+cannot allocate runs the same regrouped transport with its buffers in the
+library's fixed device array, so its results must equal the allocating
+entry point's (same histories; FP64 atomics add in another order).  Two calls
+in a row, the second on a smaller phantom with fewer histories, so a stale
+tally or counter from the first would show; free device memory does not move
+across the calls; a run too large for the array is refused."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_0910_0329_amd.inputs import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    from paper_0910_0329_amd.mcdose import Engine
+    assert torch.cuda.is_available()
+    e = Engine(0)
+    yield e
+    e.close()
+
+
+def test_noalloc_equals_simulate_on_two_calls(eng, blob):
+    import torch
+    th = eng.load_materials(blob)
+    big = configs.photon_6mv_wbw(1_000_000)
+    small = configs.electron_20mev_wlw(100_000)
+    cases = [(big, eng.load_phantom(big.phantom, th)), (small, eng.load_phantom(small.phantom, th))]
+    bufs = {w.name: [torch.empty(w.phantom.n_vox, dtype=torch.float64, device="cuda") for _ in range(3)]
+            for w, _ in cases}
+    # warm-up: first launches load the code objects
+    w0, p0 = cases[1]
+    d, s, S = bufs[w0.name]
+    eng.simulate_noalloc(p0, w0.source, 1000, w0.seed, w0.request_key, dose=d, sigma=s, S=S)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    got = []
+    for w, p in cases:
+        d, s, S = bufs[w.name]
+        log(f"case noalloc {w.name} n={w.n_histories}")
+        r = eng.simulate_noalloc(p, w.source, w.n_histories, w.seed, w.request_key, dose=d, sigma=s, S=S)
+        got.append((r, d.cpu().numpy(), s.cpu().numpy(), S.cpu().numpy()))
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] == free0
+    for (w, p), (r, d, s, S) in zip(cases, got):
+        ref = eng.simulate(p, w.source, w.n_histories, w.seed, w.request_key, n_vox=w.phantom.n_vox,
+                           want_tallies=True)
+        np.testing.assert_allclose(S, ref["S"].cpu().numpy(), rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(d, ref["dose"].cpu().numpy(), rtol=1e-9, atol=1e-25)
+        np.testing.assert_allclose(s, ref["sigma"].cpu().numpy(), rtol=1e-6, atol=1e-25)
+        assert r["dmax"] == pytest.approx(ref["dmax"], rel=1e-9)
+        assert r["sigma_bar"] == pytest.approx(ref["sigma_bar"], rel=1e-6)
+        assert r["bal"]["E_src"] == pytest.approx(ref["bal"]["E_src"], rel=1e-12)
+        assert r["bal"]["E_csda"] == pytest.approx(ref["bal"]["E_csda"], rel=1e-9)
+        assert r["n_histories"] == w.n_histories
+        log(f"  {w.name}: dmax {r['dmax']:.4e} sigma-bar {r['sigma_bar']:.4f} kernel {r['kernel_ms']:.2f} ms")
+    for _, p in cases:
+        eng.unload_phantom(p)
+    eng.unload_materials(th)
+
+
+def test_noalloc_refuses_what_does_not_fit(eng, blob):
+    import torch
+    from paper_0910_0329_amd.mcdose import E_INVAL, McdError
+    th = eng.load_materials(blob)
+    w = configs.photon_6mv_random_field(1000)        # 1.05e7 voxels: 1.3 GB of FP64 sub-tallies
+    p = eng.load_phantom(w.phantom, th)
+    d = torch.empty(w.phantom.n_vox, dtype=torch.float64, device="cuda")
+    s = torch.empty_like(d)
+    with pytest.raises(McdError) as ei:
+        eng.simulate_noalloc(p, w.source, 1000, w.seed, dose=d, sigma=s)
+    assert ei.value.status == E_INVAL and "bytes of scratch" in str(ei.value)
+    with pytest.raises(McdError) as ei:
+        eng.simulate_noalloc(p, w.source, 1000, w.seed, dose=d, sigma=s, use_graph=1)
+    assert ei.value.status == E_INVAL
+    eng.unload_phantom(p)
+    eng.unload_materials(th)
