@@ -159,7 +159,11 @@ typedef struct {
     int32_t regroup;          /* regrouped kernel schedule: 0 = default, 1 = cross-type
                                  secondaries go through the photon/electron queues, 2 = they
                                  stay on the lane's own stack (one lane transports a whole
-                                 history; the phases then only split new histories) */
+                                 history; the phases then only split new histories), 3 = the
+                                 secondaries of a wave's 64 lanes go on two stacks of the wave,
+                                 one per particle type, from which any of its lanes takes the
+                                 kind the wave is running; photon lanes park their photons to
+                                 take waiting electrons (stacks of 16 x stack_depth records) */
     /* Wave schedule of both kernels: each iteration a wave runs one kind of
      * step for the lanes that need it.  Fetching a particle runs when at
      * least 1/fetch_div of the wave's live lanes need one, sampling hard

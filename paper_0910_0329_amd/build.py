@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmcdose.so")
 SOURCES = ("k_plain.hip", "k_regroup.hip", "k_final.hip", "k_check.hip", "runtime.hip", "sched.hip",
-           "serve.hip", "noalloc.hip")
+           "serve.hip", "noalloc.hip", "k_wave.hip")
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
@@ -29,7 +29,8 @@ HIPCC_FLAGS = [
 # refinement code: k_plain<false, REF>, k_phase<false, PHOTONS, REF>
 HOT_KERNELS = ("_ZN3mcd7k_plainILb0ELb0EEEvNS_6KPlainE", "_ZN3mcd7k_plainILb0ELb1EEEvNS_6KPlainE",
                "_ZN3mcd7k_phaseILb0ELb0ELb0EEEvNS_6KPhaseE", "_ZN3mcd7k_phaseILb0ELb0ELb1EEEvNS_6KPhaseE",
-               "_ZN3mcd7k_phaseILb0ELb1ELb0EEEvNS_6KPhaseE", "_ZN3mcd7k_phaseILb0ELb1ELb1EEEvNS_6KPhaseE")
+               "_ZN3mcd7k_phaseILb0ELb1ELb0EEEvNS_6KPhaseE", "_ZN3mcd7k_phaseILb0ELb1ELb1EEEvNS_6KPhaseE",
+               "_ZN3mcd6k_waveILb0ELb0EEEvNS_6KPhaseE", "_ZN3mcd6k_waveILb0ELb1EEEvNS_6KPhaseE")
 
 
 def resource_usage(asm: str) -> dict:

@@ -136,6 +136,7 @@ struct KPhase {
 
 size_t plain_lane_bytes(int stack_depth, int slots);
 size_t phase_lane_bytes(int stack_depth);
+size_t wave_stack_bytes(int cap);
 int transport_lds_bytes(int n_mat);
 
 // Launchers.
@@ -143,6 +144,7 @@ int transport_lds_bytes(int n_mat);
 hipError_t launch_plain(const KPlain& p, int blocks, int threads, bool diag, hipStream_t s);
 hipError_t launch_phase(const KPhase& p, bool photons, int blocks, int threads, bool diag,
                         hipStream_t s);
+hipError_t launch_wave(const KPhase& p, int blocks, int threads, bool diag, hipStream_t s);
 hipError_t launch_finalize(const double* S, const double* Q, const uint2* vox, int64_t nv,
                            double vol, uint64_t n, double* dose, double* sigma, double* red,
                            hipStream_t s);
@@ -166,5 +168,6 @@ hipError_t init_kernels(int max_lds);
 hipError_t init_plain_kernels(int max_lds);
 hipError_t init_phase_kernels(int max_lds);
 hipError_t init_check_kernels(int max_lds);
+hipError_t init_wave_kernels(int max_lds);
 
 }  // namespace mcd

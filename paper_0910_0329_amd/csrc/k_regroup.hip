@@ -275,6 +275,7 @@ hipError_t init_kernels(int max_lds)
 {
     hipError_t e = init_plain_kernels(max_lds);
     if (e == hipSuccess) e = init_phase_kernels(max_lds);
+    if (e == hipSuccess) e = init_wave_kernels(max_lds);
     return e == hipSuccess ? init_check_kernels(max_lds) : e;
 }
 

@@ -1,0 +1,419 @@
+// Wave-stack transport: the regrouped engine with the secondary stacks of a
+// wave's 64 lanes pooled by particle type.
+//
+// Each wave owns two stacks in global memory, one of photons and one of
+// electrons and positrons.  A secondary goes on the stack of its type, and a
+// lane that needs a particle takes one of the type most of the wave is
+// running, so any lane can carry on any of the wave's particles.  A photon
+// can also be parked mid-flight (its record keeps the position, direction,
+// energy, stream counter and the random block in use): when the wave runs an
+// electron step and electrons wait on the stack, photon lanes park their
+// photons and take electrons, so the electron step runs with more lanes.
+// The wave drifts between photon-heavy and electron-heavy stretches instead
+// of running every kind of step with a fraction of its lanes.
+//
+// A particle's stream and tally depend only on its own lineage and history
+// index, so which lane carries a particle, and when, does not change any
+// result: the histories are those of every other kernel.  The stack counts
+// live in LDS (one pair per wave, touched only by that wave), the records in
+// global memory; the wave's own instruction stream orders every push before
+// the pops that follow it.
+#include "transport.h"
+
+namespace mcd {
+
+constexpr int kWaveRec = 64;         // bytes per wave-stack record
+enum { WS_PHOTON = 0, WS_ELECTRON = 1 };
+
+// Record of a wave stack, four float4:
+//   f0 = (x, y, z, E), f1 = (u, v, w, bits(type | slot << 4 | nsp << 16)),
+//   f2 = bits(l0, l1, h, d | ring << 31 | parked << 30), f3 = words of random
+// block d >> 2 (a parked photon that had drawn from it; ring = 1).  A fresh
+// secondary has d = 0 and nsp = 0 (its spawn count is not set yet) and leaves
+// f3 unwritten.
+DEV void store_wave_rec(char* base, const Part& q, bool parked)
+{
+    float4* r = (float4*)base;
+    const bool ring = parked && (q.d >> 2) < q.g;
+    const uint32_t nsp = parked ? q.nsp : 0u;
+    r[0] = make_float4(q.x, q.y, q.z, q.e);
+    r[1] = make_float4(q.u, q.v, q.w, __uint_as_float((uint32_t)q.type | (q.slot << 4) | (nsp << 16)));
+    r[2] = make_float4(__uint_as_float(q.l0), __uint_as_float(q.l1), __uint_as_float(q.h),
+                       __uint_as_float(q.d | (ring ? 0x80000000u : 0u) | (parked ? 0x40000000u : 0u)));
+    if (ring) {
+        const bool hi = ((q.d >> 2) & 1u) != 0;
+        r[3] = hi ? make_float4(__uint_as_float(q.r4), __uint_as_float(q.r5), __uint_as_float(q.r6),
+                                __uint_as_float(q.r7))
+                  : make_float4(__uint_as_float(q.r0), __uint_as_float(q.r1), __uint_as_float(q.r2),
+                                __uint_as_float(q.r3));
+    }
+}
+
+// Returns true when the record was parked mid-flight (its random block, if it
+// had drawn from one, restored).
+DEV bool load_wave_rec(const char* base, Part& q)
+{
+    const float4* r = (const float4*)base;
+    const float4 a = r[0], b = r[1], c = r[2];
+    q.x = a.x; q.y = a.y; q.z = a.z; q.e = a.w;
+    q.u = b.x; q.v = b.y; q.w = b.z;
+    const uint32_t ts = __float_as_uint(b.w);
+    q.type = (int)(ts & 15u);
+    q.slot = (ts >> 4) & 0xFFFu;
+    q.nsp = ts >> 16;
+    q.l0 = __float_as_uint(c.x);
+    q.l1 = __float_as_uint(c.y);
+    q.h = __float_as_uint(c.z);
+    const uint32_t dw = __float_as_uint(c.w);
+    q.d = dw & 0x3FFFFFFFu;
+    q.pend = 0;
+    q.g = q.d >> 2;
+    if (dw >> 31) {
+        const float4 w = r[3];
+        const uint32_t w0 = __float_as_uint(w.x), w1 = __float_as_uint(w.y), w2 = __float_as_uint(w.z),
+                       w3 = __float_as_uint(w.w);
+        if (q.g & 1u) {
+            q.r4 = w0; q.r5 = w1; q.r6 = w2; q.r7 = w3;
+        } else {
+            q.r0 = w0; q.r1 = w1; q.r2 = w2; q.r3 = w3;
+        }
+        ++q.g;
+    }
+    return ((dw >> 30) & 1u) != 0;
+}
+
+template <bool DIAG, bool REF>
+struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
+    using Base = Transport<WaveLane<DIAG, REF>, DIAG, REF>;
+    const KPhase& p;
+    char* base;                    // this wave's stacks: photon records, their diagnostic
+                                   // event hashes, electron records (wave-uniform)
+    volatile unsigned int* cnt;    // LDS: records on the photon and electron stacks
+    int cur_v;
+    float cur_e;
+    int slot;
+    void* tally;
+    mcd_history_record* hist;
+    uint32_t first;
+    double p_edep, p_track;
+    bool more_new;                 // wave-uniform: new histories may remain
+
+    DEV WaveLane(const KPhase& pp, char* b, volatile unsigned int* c)
+        : Base(pp.g), p(pp), base(b), cnt(c), cur_v(-1), cur_e(0.f), slot(-1), tally(nullptr), hist(nullptr),
+          first(0), p_edep(0.0), p_track(0.0), more_new(true) {}
+
+    DEV unsigned cap() const { return (unsigned)p.stack_depth; }
+    DEV char* rec(int k, unsigned i) const
+    {
+        const size_t off = k == WS_PHOTON ? 0 : (size_t)cap() * (kWaveRec + sizeof(uint64_t));
+        return base + off + (size_t)i * kWaveRec;
+    }
+    DEV uint64_t* phash() const { return (uint64_t*)(base + (size_t)cap() * kWaveRec); }
+
+    DEV void fail(int status)
+    {
+        this->failed = 1;
+        atomicCAS(p.err, 0, status);
+    }
+
+    DEV void use_request(uint32_t s)
+    {
+        if ((int)s == slot) return;
+        const ReqDev& r = p.req[s];
+        slot = (int)s;
+        this->env.seed = r.seed;
+        this->env.key = r.key;
+        tally = r.tally;
+        hist = (mcd_history_record*)r.hist;
+        first = r.first;
+    }
+
+    // ------------------------------------------------------------- tally
+    DEV void flush_visit(const Part& q)
+    {
+        if (cur_v < 0) return;
+        const size_t idx = (size_t)(q.h & (kBatches - 1)) * (size_t)p.nv + (size_t)cur_v;
+        if (p.tally_fp32) unsafeAtomicAdd((float*)tally + idx, cur_e);
+        else unsafeAtomicAdd((double*)tally + idx, (double)cur_e);
+        if (DIAG) ++this->c[MCD_C_FLUSHES];
+        cur_v = -1;
+    }
+
+    DEV void deposit(const Part& q, int v, float e)
+    {
+        if (e == 0.f) return;
+        if (DIAG) p_edep += (double)e;
+        if (v == cur_v) {
+            cur_e += e;
+        } else {
+            flush_visit(q);
+            cur_v = v;
+            cur_e = e;
+        }
+    }
+
+    DEV void flush_particle(const Part& q)
+    {
+        flush_visit(q);
+        if (DIAG && hist && p_edep != 0.0) unsafeAtomicAdd(&hist[q.h - first].edep, p_edep);
+        p_edep = 0.0;
+    }
+
+    DEV void add_track(const Part&, float l) { if (DIAG) p_track += (double)l; }
+
+    DEV void escaped(const Part& q)
+    {
+        if (DIAG && hist) atomicMax(&hist[q.h - first].escaped, 1u);
+    }
+
+    DEV void particle_done(const Part& q, uint64_t ph)
+    {
+        flush_visit(q);
+        if (DIAG && hist) {
+            mcd_history_record* r = &hist[q.h - first];
+            if (p_edep != 0.0) unsafeAtomicAdd(&r->edep, p_edep);
+            if (p_track != 0.0) unsafeAtomicAdd(&r->track_e, p_track);
+            atomicAdd((unsigned long long*)&r->hash, (unsigned long long)ph);
+            atomicAdd(&r->n_particles, 1u);
+        }
+        p_edep = p_track = 0.0;
+    }
+
+    // ------------------------------------------------------- wave stacks
+    // Pushes the calling lanes' particles onto stack k.  The active lanes may
+    // be any subset of the wave: they read the count from LDS, place their
+    // records after it by rank and all write back the same new count.
+    DEV void push(int k, const Part& s, bool parked, uint64_t hash)
+    {
+        const uint64_t m = __builtin_amdgcn_ballot_w64(true);
+        const unsigned rank =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        const unsigned top0 = cnt[k];
+        const unsigned i = top0 + rank;
+        if (i < cap()) {
+            store_wave_rec(rec(k, i), s, parked);
+            if (DIAG && k == WS_PHOTON) phash()[i] = parked ? hash : 0ull;
+        } else {
+            fail(MCD_E_OVERFLOW);
+        }
+        const unsigned top = min(top0 + (unsigned)__popcll(m), cap());
+        cnt[k] = top;
+        if (DIAG && top > this->c[MCD_C_MAX_STACK]) this->c[MCD_C_MAX_STACK] = top;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    }
+
+    DEV void spawn(const Part& s) { push(s.type == PHOTON ? WS_PHOTON : WS_ELECTRON, s, false, 0ull); }
+
+    // Takes record i of stack k into q and starts it (a parked photon resumes
+    // where it stopped, with its event hash; a fresh particle starts anew).
+    DEV bool take(int k, unsigned i, Part& q)
+    {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const bool parked = load_wave_rec(rec(k, i), q);
+        if (q.type < PHOTON || q.type > POSITRON || (int)q.slot >= p.n_req) {
+            fail(MCD_E_DEVICE);
+            q.type = DEAD;
+            return false;
+        }
+        use_request(q.slot);
+        if (parked) {
+            q.pend = 0;
+            if (DIAG) this->p_hash = phash()[i];
+        } else {
+            this->start_particle(q);
+        }
+        return true;
+    }
+
+    // Parks the lane's photon (mid-flight) on the photon stack.
+    DEV void park(Part& q)
+    {
+        flush_particle(q);
+        push(WS_PHOTON, q, true, DIAG ? this->p_hash : 0ull);
+        q.type = DEAD;
+    }
+
+    // Claims the next new history; false when none is left.  Its primary
+    // starts on this lane, whatever its kind.
+    DEV bool claim(Part& q)
+    {
+        const unsigned int j = wave_fetch_add(&p.claim[p.cycle]);
+        const uint64_t gi = (uint64_t)p.cycle * p.chunk + j;
+        if ((uint64_t)j >= p.chunk || gi >= p.total) return false;
+        int lo = 0, hi = p.n_req - 1;          // last request whose first index <= gi
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (p.req[mid].lo <= gi) lo = mid; else hi = mid - 1;
+        }
+        const ReqDev& r = p.req[lo];
+        use_request((uint32_t)lo);
+        q.slot = (uint32_t)lo;
+        q.h = r.first + (uint32_t)(gi - r.lo);
+        this->start_history(q, r.src, r.src.edges, r.src.cdf);
+        if (q.type == DEAD) flush_particle(q);
+        else this->start_particle(q);
+        return true;
+    }
+
+    // Fetch step of the lanes that need a particle: first the stack of the
+    // kind the wave mostly runs (electrons unless photons outnumber them),
+    // then the other stack, then new histories.  Returns false for a lane
+    // whose claim found the histories exhausted.
+    DEV bool fetch_wave(Part& q, bool prefer_photons)
+    {
+        const uint64_t m = __builtin_amdgcn_ballot_w64(true);
+        const unsigned rank =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        const unsigned nfl = (unsigned)__popcll(m);
+        const int ka = prefer_photons ? WS_PHOTON : WS_ELECTRON, kb = 1 - ka;
+        const unsigned ca = cnt[ka], cb = cnt[kb];
+        const unsigned ta = min(nfl, ca), tb = min(nfl - ta, cb);
+        cnt[ka] = ca - ta;
+        cnt[kb] = cb - tb;
+        if (rank < ta) take(ka, ca - 1 - rank, q);
+        else if (rank < ta + tb) take(kb, cb - 1 - (rank - ta), q);
+        // every record taken above is read before a new history below can
+        // push onto the slots just freed (a positron primary below its
+        // cutoff annihilates at once)
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (rank < ta + tb) return true;
+        if (!more_new || this->failed) return false;
+        return claim(q);
+    }
+
+    // ---------------------------------------------------- wave schedule
+    // As Transport::run, with the wave stacks: fetching lanes count only
+    // while a stack holds particles or new histories remain; before an
+    // electron step, photon lanes park their photons and take waiting
+    // electrons; the wave ends when no lane holds a particle and nothing is
+    // left to fetch.
+    enum { ST_FETCH, ST_PHOTON, ST_ELECTRON, ST_HARD };
+
+    DEV int state(const Part& q) const
+    {
+        return q.type == DEAD ? ST_FETCH : (q.type == PHOTON ? ST_PHOTON : (q.pend ? ST_HARD : ST_ELECTRON));
+    }
+
+    DEV void run_wave(Part& q, const Sched sc)
+    {
+        for (;;) {
+            int st = state(q);
+            const uint64_t live = __builtin_amdgcn_ballot_w64(true);
+            const int n = __popcll(live);
+            const int nf = __popcll(__builtin_amdgcn_ballot_w64(st == ST_FETCH));
+            const int np = __popcll(__builtin_amdgcn_ballot_w64(st == ST_PHOTON));
+            const int nh = __popcll(__builtin_amdgcn_ballot_w64(st == ST_HARD));
+            const int ne = n - nf - np - nh;
+            const unsigned sg = cnt[WS_PHOTON], se = cnt[WS_ELECTRON];
+            const bool avail = sg + se > 0 || more_new;
+            if (nf == n && !avail) break;
+            const int nfe = avail ? nf : 0;
+            int act;
+            if (nfe && (nfe * sc.fetch_div >= n || nfe == n)) act = ST_FETCH;
+            else if (nh && (nh * sc.hard_div >= n || nh + nf == n)) act = ST_HARD;
+            else if (np && np * sc.photon_div >= ne) act = ST_PHOTON;
+            else if (ne) act = ST_ELECTRON;
+            else act = nh ? ST_HARD : ST_FETCH;
+            if (act == ST_ELECTRON && np && se) {
+                if (st == ST_PHOTON) {
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(true);
+                    const unsigned rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    const unsigned k = min((unsigned)__popcll(m), se);
+                    if (rank < k) {
+                        park(q);
+                        take(WS_ELECTRON, se - 1 - rank, q);
+                    }
+                    cnt[WS_ELECTRON] = se - k;
+                }
+                st = state(q);
+            }
+            const int na = DIAG ? __popcll(__builtin_amdgcn_ballot_w64(st == act)) : 0;
+            if (DIAG && __builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0u)) == 0) {
+                ++this->c[MCD_C_ITERS];
+                this->c[MCD_C_LIVE] += (uint32_t)n;
+                ++this->c[MCD_C_IT_FETCH + act];
+                this->c[MCD_C_LN_FETCH + act] += (uint32_t)na;
+            }
+            bool exhausted = false;
+            if (st == act) {
+                if (act == ST_FETCH) {
+                    exhausted = !fetch_wave(q, np > ne);
+                } else if (act == ST_PHOTON) {
+                    this->photon_step(q);
+                } else if (act == ST_ELECTRON) {
+                    this->electron_step(q);
+                } else {
+                    this->hard_event(q);
+                }
+            }
+            if (__builtin_amdgcn_ballot_w64(exhausted) != 0) more_new = false;
+            if (this->failed) break;
+        }
+    }
+};
+
+template <bool DIAG, bool REF>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_wave(KPhase p)
+{
+    extern __shared__ float4 lds[];
+    Env env;
+    float* extra;
+    stage_tables(p.g, lds, env, &extra);
+    // wave-uniform: the wave's index, its LDS counters and its stacks
+    const uint32_t w_in_block = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    volatile unsigned int* wc = (volatile unsigned int*)extra + 2 * w_in_block;
+    if ((threadIdx.x & 63) == 0) {
+        wc[0] = 0u;
+        wc[1] = 0u;
+    }
+    __syncthreads();
+    const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + w_in_block;
+    WaveLane<DIAG, REF> L(p, p.scratch + wave * p.lane_bytes, wc);
+    L.env = env;
+    L.init_base();
+    Part q;
+    q.type = DEAD;
+    q.pend = 0;
+    L.run_wave(q, p.sched);
+    L.reduce_out(p.bal, p.cnt);
+}
+
+// Bytes of one wave's stacks for `cap` records per stack (photon records and
+// their diagnostic hashes, electron records).
+size_t wave_stack_bytes(int cap)
+{
+    const size_t b = (size_t)cap * (2 * kWaveRec + sizeof(uint64_t));
+    return (b + 255) & ~(size_t)255;
+}
+
+static void (*wave_kernel(int which))(KPhase)
+{
+    switch (which) {
+    case 0: return k_wave<false, false>;
+    case 1: return k_wave<false, true>;
+    case 2: return k_wave<true, false>;
+    default: return k_wave<true, true>;
+    }
+}
+
+hipError_t launch_wave(const KPhase& p, int blocks, int threads, bool diag, hipStream_t s)
+{
+    const size_t lds = transport_lds_bytes(p.g.t.n_mat);
+    const int which = (diag ? 2 : 0) | (p.g.t.refined ? 1 : 0);
+    hipLaunchKernelGGL(wave_kernel(which), dim3(blocks), dim3(threads), lds, s, p);
+    return hipGetLastError();
+}
+
+hipError_t init_wave_kernels(int max_lds)
+{
+    for (int which = 0; which < 4; ++which) {
+        const hipError_t e = hipFuncSetAttribute((const void*)wave_kernel(which),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace mcd

@@ -118,6 +118,7 @@ struct RegroupPlan {
     bool diag = false;
     bool refined_build = false;      // force the kernels built with the refinement code
     bool use_queues = false;
+    bool wave_stacks = false;        // secondaries on per-wave photon and electron stacks
     Sched sched{};
     RegroupBufs* bufs = nullptr;     // device buffers the run uses (the context's, or a
     unsigned char* small = nullptr;  // carve-out of the no-allocation scratch)
@@ -137,6 +138,10 @@ namespace mcd {
 int run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_graph, hipStream_t s);
 // Records per particle queue for cycles of `chunk` new histories.
 unsigned int queue_capacity(uint64_t chunk);
+// Device bytes of the particle stacks of `lanes` lanes at stack depth `depth`:
+// per-lane stacks, or (wave_stacks) per-wave photon and electron stacks of
+// 16 x depth records each, the same number of records per wave.
+size_t stack_scratch_bytes(uint64_t lanes, int depth, bool wave_stacks);
 // Looks up the calling thread's current device's copy of the no-allocation
 // scratch array (once per device; later calls return the first outcome).
 hipError_t noalloc_setup(int device);

@@ -212,6 +212,12 @@ unsigned int mcd::queue_capacity(uint64_t chunk)
     return (unsigned int)std::min<uint64_t>(std::max<uint64_t>(2 * chunk, 1 << 16), (uint64_t)1 << 26);
 }
 
+size_t mcd::stack_scratch_bytes(uint64_t lanes, int depth, bool wave_stacks)
+{
+    if (wave_stacks) return (size_t)((lanes + 63) / 64) * wave_stack_bytes(16 * depth);
+    return (size_t)lanes * phase_lane_bytes(depth);
+}
+
 // Histories h in [first, first + n) with h mod kBatches == b.
 static double batch_count(uint64_t first, uint64_t n, int b)
 {
@@ -243,8 +249,9 @@ int mcd_ctx::prepare_regroup(int32_t phantom, const mcd_source* const* srcs, con
     plan.n_req = n_req;
     plan.n_fin = n_req;
     plan.depth = opts && opts->stack_depth ? opts->stack_depth : kDefaultDepth;
-    if (opts && (opts->regroup < 0 || opts->regroup > 2)) return fail(MCD_E_INVAL, "opts: regroup must be 0, 1 or 2");
+    if (opts && (opts->regroup < 0 || opts->regroup > 3)) return fail(MCD_E_INVAL, "opts: regroup must be 0 to 3");
     plan.use_queues = opts && opts->regroup == 1;
+    plan.wave_stacks = opts && opts->regroup == 3;
     plan.fp32 = opts && opts->tally_fp32 ? 1 : 0;
     plan.diag = opts && opts->diagnostics;
     if (opts && (opts->refined_build < 0 || opts->refined_build > 1))
@@ -354,8 +361,8 @@ int mcd_ctx::plan_regroup(int32_t phantom, const mcd_source* const* srcs, const 
         }
         rb.stage_bytes = stage_bytes;
     }
-    if ((rc = grow((void**)&rb.scratch, &rb.scratch_bytes, lanes * phase_lane_bytes(plan.depth),
-                   "lane stacks")))
+    if ((rc = grow((void**)&rb.scratch, &rb.scratch_bytes, stack_scratch_bytes(lanes, plan.depth, plan.wave_stacks),
+                   "particle stacks")))
         return rc;
 
     for (int r = 0; r < n_req; ++r) {
@@ -414,6 +421,14 @@ int mcd_ctx::enqueue_cycles(const RegroupPlan& plan, int c0, int c1, hipStream_t
         k.q_out_ctl = Ce[a];
         k.q_reset_ctl = Cg[b];
         k.use_queues = plan.use_queues;
+        if (plan.wave_stacks) {
+            // one launch takes every history; its waves pool their stacks
+            k.stack_depth = 16 * plan.depth;
+            k.lane_bytes = wave_stack_bytes(k.stack_depth);
+            hipError_t e = launch_wave(k, plan.blocks, plan.threads, plan.diag, s);
+            if (e != hipSuccess) return hip_fail(e, "wave-stack transport launch");
+            continue;
+        }
         hipError_t e = launch_phase(k, true, plan.blocks, plan.threads, plan.diag, s);
         if (e != hipSuccess) return hip_fail(e, "photon phase launch");
         if (!plan.use_queues) continue;       // nothing is ever queued for it
@@ -587,6 +602,7 @@ int mcd::run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_g
         add(&plan.diag, sizeof plan.diag);
         add(&plan.refined_build, sizeof plan.refined_build);
         add(&plan.use_queues, sizeof plan.use_queues);
+        add(&plan.wave_stacks, sizeof plan.wave_stacks);
         add(&plan.sched, sizeof plan.sched);
         add(&clear_tally, sizeof clear_tally);
         add(&c->rb, sizeof c->rb);

@@ -162,7 +162,7 @@ static void admit(mcd_ctx* c, mcd_server* S)
         size_t reserve = (size_t)1 << 20;
         if (c->launch_shape(&S->cfg.opts, c->tables[ph.tables].n_mat, &blocks, &threads) == MCD_OK) {
             const uint64_t lanes = (uint64_t)blocks * threads;
-            const size_t lanes_b = lanes * phase_lane_bytes(depth);
+            const size_t lanes_b = stack_scratch_bytes(lanes, depth, S->cfg.opts.regroup == 3);
             if (lanes_b > c->rb.scratch_bytes) reserve += lanes_b - c->rb.scratch_bytes;
             if (S->cfg.opts.regroup == 1) {
                 const int cpl = S->cfg.opts.chunk_per_lane ? S->cfg.opts.chunk_per_lane : kDefaultChunkPerLane;
@@ -441,7 +441,7 @@ static int check_config(mcd_ctx* c, const mcd_serve_config* cfg)
         o.kernel != MCD_KERNEL_REGROUPED || o.tally_slots)
         return c->fail(MCD_E_INVAL, "serve config: first_history, accumulate, history_records, lockstep, "
                                     "use_graph and tally_slots must be 0 and kernel regrouped");
-    if (o.regroup < 0 || o.regroup > 2) return c->fail(MCD_E_INVAL, "serve config: regroup must be 0, 1 or 2");
+    if (o.regroup < 0 || o.regroup > 3) return c->fail(MCD_E_INVAL, "serve config: regroup must be 0 to 3");
     if (o.stack_depth && (o.stack_depth < 4 || o.stack_depth > 4096))
         return c->fail(MCD_E_INVAL, "serve config: stack_depth in [4, 4096]");
     if (o.chunk_per_lane < 0 || o.chunk_per_lane > 4096)

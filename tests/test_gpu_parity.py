@@ -24,7 +24,7 @@ from paper_0910_0329_amd.inputs import configs, phantoms, sources
 from paper_0910_0329_amd.inputs.sources import ELECTRON, PHOTON, POSITRON
 
 pytestmark = pytest.mark.gpu
-KERNELS = ("plain", "regrouped", "queued")
+KERNELS = ("plain", "regrouped", "queued", "wave")
 
 
 def log(msg):
@@ -49,11 +49,12 @@ def th(eng, blob):
 
 def kopt(kernel):
     """Run options of a kernel variant: the plain per-history kernel, the
-    regrouped kernel with lane stacks, or with photon/electron queues."""
+    regrouped kernel with lane stacks, with photon/electron queues, or with
+    per-wave stacks by particle type."""
     from paper_0910_0329_amd.mcdose import KERNEL_PLAIN, KERNEL_REGROUPED
     if kernel == "plain":
         return {"kernel": KERNEL_PLAIN}
-    return {"kernel": KERNEL_REGROUPED, "regroup": 1 if kernel == "queued" else 2}
+    return {"kernel": KERNEL_REGROUPED, "regroup": {"queued": 1, "regrouped": 2, "wave": 3}[kernel]}
 
 
 def run_both(eng, blob, th, ph, src, n, seed, key=0, kernel="plain", diag=True, **opts):
@@ -177,7 +178,7 @@ def angular(eng):
     return blob, eng.load_materials(blob)
 
 
-@pytest.mark.parametrize("kernel", ("plain", "regrouped"))
+@pytest.mark.parametrize("kernel", ("plain", "regrouped", "wave"))
 @pytest.mark.parametrize("particle,e,n,gate", [(PHOTON, 18.0, 6_000, 0.975), (ELECTRON, 15.0, 3_000, 0.925),
                                                (PHOTON, 0.6, 40_000, 0.99)])   # measured 0.9930, 0.9457, 1.0
 def test_angular_tables_match_oracle(eng, angular, particle, e, n, gate, kernel):
@@ -197,7 +198,7 @@ def test_angular_tables_match_oracle(eng, angular, particle, e, n, gate, kernel)
     assert g["cnt"]["photo"] + g["cnt"]["pair"] + g["cnt"]["brems"] > 0
 
 
-@pytest.mark.parametrize("kernel", ("plain", "regrouped"))
+@pytest.mark.parametrize("kernel", ("plain", "regrouped", "wave"))
 def test_density_effect_tables_match_oracle(eng, kernel):
     """Tables with the density effect in the collision stopping power: the
     same transport code on different ranges and stopping powers."""
@@ -215,7 +216,7 @@ def test_density_effect_tables_match_oracle(eng, kernel):
     eng.unload_materials(thd)
 
 
-@pytest.mark.parametrize("kernel", ("plain", "regrouped"))
+@pytest.mark.parametrize("kernel", ("plain", "regrouped", "wave"))
 @pytest.mark.parametrize("middle,gate", [("lung", 0.88), ("bone", 0.925)])   # measured 0.9040, 0.9450
 def test_per_element_screening_tables_match_oracle(eng, kernel, middle, gate):
     """Tables whose elastic cross sections screen each element by its own
@@ -236,7 +237,7 @@ def test_per_element_screening_tables_match_oracle(eng, kernel, middle, gate):
     eng.unload_materials(the)
 
 
-@pytest.mark.parametrize("kernel", ("plain", "regrouped"))
+@pytest.mark.parametrize("kernel", ("plain", "regrouped", "wave"))
 @pytest.mark.parametrize("variant,particle,e,n,gate", [("rayleigh", PHOTON, 0.15, 60_000, 0.99),
                                                        ("refined", PHOTON, 0.25, 60_000, 0.99),
                                                        ("refined", PHOTON, 6.0, 30_000, 0.98)])
@@ -262,7 +263,7 @@ def test_rayleigh_tables_match_oracle(eng, variant, particle, e, n, gate, kernel
     assert abs(nr - nr_ref) <= 0.05 * nr_ref + 10
 
 
-@pytest.mark.parametrize("kernel", ("plain", "regrouped"))
+@pytest.mark.parametrize("kernel", ("plain", "regrouped", "wave"))
 @pytest.mark.parametrize("variant,particle,e,n,gate", [("hinge2", ELECTRON, 12.0, 4_000, 0.935),
                                                        ("hinge2", PHOTON, 8.0, 30_000, 0.98),
                                                        ("refined", ELECTRON, 18.0, 3_000, 0.905),
@@ -295,7 +296,7 @@ def test_second_moment_hinge_tables_match_oracle(eng, variant, particle, e, n, g
     assert g["cnt"]["hinges"] == pytest.approx(ref["cnt"]["hinges"], rel=0.02)
 
 
-@pytest.mark.parametrize("kernel", ("plain", "regrouped", "queued"))
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("variant,particle,e,n,gate", [("bhabha", POSITRON, 12.0, 4_000, 0.94),
                                                        ("bhabha", POSITRON, 0.9, 20_000, 0.985),
                                                        ("refined", POSITRON, 6.0, 4_000, 0.965),
@@ -361,7 +362,7 @@ def test_kernels_agree_on_histories(eng, blob, th):
         out[kernel] = r
     eng.unload_phantom(pid)
     a = out["plain"]
-    for other in ("regrouped", "queued"):
+    for other in ("regrouped", "queued", "wave"):
         b = out[other]
         same = a["hist"]["hash"] == b["hist"]["hash"]
         log(f"  plain vs {other}: {same.mean():.5f} of histories identical")
