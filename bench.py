@@ -48,12 +48,13 @@ PATH_LANE_OPS = {
 # Plain VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # = 3.93e13 lane-ops/s (one non-packed FP32/INT32 op per lane per cycle).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-# HBM bytes per history of the transport kernel: rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, each scaled by its reading for a 1 GiB device copy
-# (profiles/transport_g6mv_hbm_traffic.md, profiles/transport_e20_wlw_hbm_traffic.md).
+# HBM bytes per history of the transport kernel (the wave-stack kernel
+# k_wave<false, false>): rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by
+# its reading for a 1 GiB device copy (profiles/transport_g6mv_hbm_traffic.md,
+# profiles/transport_e20_wlw_hbm_traffic.md).
 TRAFFIC_BYTES_PER_HIST = {
-    "g6mv_wbw_61x61x60": (11386401.8125 * 2.0 + 34976274.59375 * 1.0) * 1024 / 155871405,   # 379.4
-    "e20_wlw_32x32x30": (2615060.375 * 2.0 + 17980546.21875 * 1.0) * 1024 / 10_000_000,     # 2376.8
+    "g6mv_wbw_61x61x60": (17239292.44 * 2.0 + 46302278.0 * 1.0) * 1024 / 164442762,    # 503.0
+    "e20_wlw_32x32x30": (765361.75 * 2.0 + 16117193.66 * 1.0) * 1024 / 10_000_000,     # 1807.1
 }
 METRIC = "histories/s (6 MV photon, 20 MeV e-) at 1% sigma; p50/p99 dose-request latency"
 # The paper's Table 1 (Tesla C1060, FP32; DPM physics and a measured 6 MV
@@ -236,7 +237,8 @@ def main():
                           "launches": re_["launches"],
                           "per_launch_ms": re_["kernel_ms"] / max(re_["launches"], 1),
                           "alu_frac": pe_path * we.n_histories / k_s / PEAK_LANE_OPS,
-                          "traffic": TRAFFIC_BYTES_PER_HIST[we.name] * we.n_histories / max(re_["launches"], 1),
+                          "traffic": (TRAFFIC_BYTES_PER_HIST[we.name] * we.n_histories / max(re_["launches"], 1)
+                                      if we.name in TRAFFIC_BYTES_PER_HIST else None),
                           "energy_balance_rel": closure(re_["bal"])}), flush=True)
         eng.close()
         return
@@ -280,7 +282,8 @@ def main():
         "config": {"workload": wg.name,
                    "source": "6 MV spectrum (64 bins, 0.1-6 MeV), point source SSD 100 cm, 10x10 cm field",
                    "phantom": "61x61x60 x 0.5 cm: water 0-3 cm, bone 1.85 g/cm3 3-7 cm, water 7-30 cm",
-                   "kernel": "regrouped (lane stacks; 16 sub-tallies, batch statistics)",
+                   "kernel": "regrouped (wave stacks by particle type, photon/electron modes; 16 sub-tallies, "
+                             "batch statistics)",
                    "histories_per_step": n1, "sigma_bar": sbar, "sigma_bar_exact": rp["sigma_bar"],
                    "sigma_bar_estimators": "sigma_bar: the regrouped kernel's 16-group estimate (c4-corrected); "
                                            "sigma_bar_exact: history-by-history (plain kernel) at the same N",
@@ -291,7 +294,7 @@ def main():
     }
 
     path = PATH_LANE_OPS.get(wg.name)
-    roofline = {"bound": "alu", "kernel": "k_phase<false,true,false> (photon phase)", "achieved": None,
+    roofline = {"bound": "alu", "kernel": "k_wave<false,false> (wave-stack transport)", "achieved": None,
                 "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s", "frac": None, "traffic": None,
                 "per_launch_ms": k_ms / max(launches, 1), "histories_per_launch": n1 / max(launches, 1)}
     if path:

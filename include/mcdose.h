@@ -156,21 +156,25 @@ typedef struct {
                                  and cycle, 0 = 16; with lane stacks one launch takes them all */
     int32_t use_graph;        /* regrouped kernel: capture the launch sequence in a hipGraph
                                  and replay it when the same call is repeated */
-    int32_t regroup;          /* regrouped kernel schedule: 0 = default, 1 = cross-type
+    int32_t regroup;          /* regrouped kernel schedule: 0 = default (3), 1 = cross-type
                                  secondaries go through the photon/electron queues, 2 = they
                                  stay on the lane's own stack (one lane transports a whole
                                  history; the phases then only split new histories), 3 = the
                                  secondaries of a wave's 64 lanes go on two stacks of the wave,
-                                 one per particle type, from which any of its lanes takes the
-                                 kind the wave is running; photon lanes park their photons to
-                                 take waiting electrons (stacks of 16 x stack_depth records) */
+                                 one per particle type; the wave runs in a photon or an
+                                 electron mode, and lanes holding the other kind park their
+                                 particle mid-flight and take a waiting one of the mode's kind
+                                 (stacks of 16 x stack_depth records per wave) */
     /* Wave schedule of both kernels: each iteration a wave runs one kind of
      * step for the lanes that need it.  Fetching a particle runs when at
      * least 1/fetch_div of the wave's live lanes need one, sampling hard
      * events when 1/hard_div wait for it, photon flights when photons are at
      * least electrons/photon_div; else electron segments.  1..64, 0 = default:
-     * plain kernel (3, 24, 2); regrouped kernel (3, 24, 2) when every source
-     * is a photon source, else (4, 8, 6). */
+     * plain kernel (3, 24, 2); regrouped kernel with lane stacks or queues
+     * (3, 24, 2) when every source is a photon source, else (4, 8, 6); with
+     * wave stacks (regroup 0 or 3) (4, 24, 1) or (6, 8, 1), where photon_div
+     * instead sets the mode switch (the mode's work below 64 / photon_div
+     * lanes). */
     int32_t sched_fetch_div;
     int32_t sched_hard_div;
     int32_t sched_photon_div;

@@ -2,15 +2,18 @@
 // wave's 64 lanes pooled by particle type.
 //
 // Each wave owns two stacks in global memory, one of photons and one of
-// electrons and positrons.  A secondary goes on the stack of its type, and a
-// lane that needs a particle takes one of the type most of the wave is
-// running, so any lane can carry on any of the wave's particles.  A photon
-// can also be parked mid-flight (its record keeps the position, direction,
-// energy, stream counter and the random block in use): when the wave runs an
-// electron step and electrons wait on the stack, photon lanes park their
-// photons and take electrons, so the electron step runs with more lanes.
-// The wave drifts between photon-heavy and electron-heavy stretches instead
-// of running every kind of step with a fraction of its lanes.
+// electrons and positrons.  A secondary goes on the stack of its type, and any
+// lane of the wave can carry on any of the wave's particles.  A particle can
+// also be parked mid-flight: its record keeps the position, direction,
+// energy, stream counter and the random block in use, and for an electron its
+// voxel, hinge and hard-event state.  The wave works in a photon or an
+// electron mode: lanes that need a particle take one of the mode's kind, and
+// lanes that hold the other kind park it and take a waiting particle of the
+// mode's kind, so the mode's steps run with the whole wave.  The mode changes
+// when its kind no longer has work for a good part of the wave (lanes plus
+// stacked particles below 64 / photon_div) and the other kind has more.  A
+// new history starts only while the two stacks together hold fewer than a
+// quarter of their capacity, which bounds the particles a wave holds.
 //
 // A particle's stream and tally depend only on its own lineage and history
 // index, so which lane carries a particle, and when, does not change any
@@ -22,7 +25,8 @@
 
 namespace mcd {
 
-constexpr int kWaveRec = 64;         // bytes per wave-stack record
+constexpr int kWaveRec = 80;         // bytes per photon-stack record
+constexpr int kWaveERec = 112;       // bytes per electron-stack record (with the electron state)
 enum { WS_PHOTON = 0, WS_ELECTRON = 1 };
 
 // Record of a wave stack, four float4:
@@ -30,7 +34,11 @@ enum { WS_PHOTON = 0, WS_ELECTRON = 1 };
 //   f2 = bits(l0, l1, h, d | ring << 31 | parked << 30), f3 = words of random
 // block d >> 2 (a parked photon that had drawn from it; ring = 1).  A fresh
 // secondary has d = 0 and nsp = 0 (its spawn count is not set yet) and leaves
-// f3 unwritten.
+// f3 unwritten.  A parked particle also keeps its open tally visit (the voxel
+// and the FP32 sum of its deposits there so far), so that its deposits are
+// grouped as if it had never stopped: f4 = (bits(cur_v), cur_e, flags, 0), and
+// an electron f5 = bits(ix, iy, iz, 0), f6 = (nh, xi, kap, 0), flags = before
+// | pend << 1.
 DEV void store_wave_rec(char* base, const Part& q, bool parked)
 {
     float4* r = (float4*)base;
@@ -46,6 +54,37 @@ DEV void store_wave_rec(char* base, const Part& q, bool parked)
                                 __uint_as_float(q.r7))
                   : make_float4(__uint_as_float(q.r0), __uint_as_float(q.r1), __uint_as_float(q.r2),
                                 __uint_as_float(q.r3));
+    }
+}
+
+DEV void store_parked_state(char* base, const Part& q, int cur_v, float cur_e, bool electron)
+{
+    float4* r = (float4*)base;
+    const uint32_t flags = electron ? ((uint32_t)q.before | ((uint32_t)q.pend << 1)) : 0u;
+    r[4] = make_float4(__int_as_float(cur_v), cur_e, __uint_as_float(flags), 0.f);
+    if (electron) {
+        r[5] = make_float4(__int_as_float(q.ix), __int_as_float(q.iy), __int_as_float(q.iz), 0.f);
+        r[6] = make_float4(q.nh, q.xi, q.kap, 0.f);
+    }
+}
+
+DEV void load_parked_state(const char* base, Part& q, int& cur_v, float& cur_e, bool electron)
+{
+    const float4* r = (const float4*)base;
+    const float4 a = r[4];
+    cur_v = __float_as_int(a.x);
+    cur_e = a.y;
+    if (electron) {
+        const uint32_t f = __float_as_uint(a.z);
+        q.before = (int)(f & 1u);
+        q.pend = (int)((f >> 1) & 1u);
+        const float4 b = r[5], c = r[6];
+        q.ix = __float_as_int(b.x);
+        q.iy = __float_as_int(b.y);
+        q.iz = __float_as_int(b.z);
+        q.nh = c.x;
+        q.xi = c.y;
+        q.kap = c.z;
     }
 }
 
@@ -102,13 +141,18 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
         : Base(pp.g), p(pp), base(b), cnt(c), cur_v(-1), cur_e(0.f), slot(-1), tally(nullptr), hist(nullptr),
           first(0), p_edep(0.0), p_track(0.0), more_new(true) {}
 
+    // layout: photon records | their hashes | electron records | their hashes
     DEV unsigned cap() const { return (unsigned)p.stack_depth; }
     DEV char* rec(int k, unsigned i) const
     {
-        const size_t off = k == WS_PHOTON ? 0 : (size_t)cap() * (kWaveRec + sizeof(uint64_t));
-        return base + off + (size_t)i * kWaveRec;
+        if (k == WS_PHOTON) return base + (size_t)i * kWaveRec;
+        return base + (size_t)cap() * (kWaveRec + sizeof(uint64_t)) + (size_t)i * kWaveERec;
     }
-    DEV uint64_t* phash() const { return (uint64_t*)(base + (size_t)cap() * kWaveRec); }
+    DEV uint64_t* hashes(int k) const
+    {
+        if (k == WS_PHOTON) return (uint64_t*)(base + (size_t)cap() * kWaveRec);
+        return (uint64_t*)(base + (size_t)cap() * (kWaveRec + sizeof(uint64_t) + kWaveERec));
+    }
 
     DEV void fail(int status)
     {
@@ -192,7 +236,8 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
         const unsigned i = top0 + rank;
         if (i < cap()) {
             store_wave_rec(rec(k, i), s, parked);
-            if (DIAG && k == WS_PHOTON) phash()[i] = parked ? hash : 0ull;
+            if (parked) store_parked_state(rec(k, i), s, cur_v, cur_e, k == WS_ELECTRON);
+            if (DIAG) hashes(k)[i] = hash;
         } else {
             fail(MCD_E_OVERFLOW);
         }
@@ -204,8 +249,8 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
 
     DEV void spawn(const Part& s) { push(s.type == PHOTON ? WS_PHOTON : WS_ELECTRON, s, false, 0ull); }
 
-    // Takes record i of stack k into q and starts it (a parked photon resumes
-    // where it stopped, with its event hash; a fresh particle starts anew).
+    // Takes record i of stack k into q and starts it (a parked particle
+    // resumes where it stopped, with its event hash; a fresh one starts anew).
     DEV bool take(int k, unsigned i, Part& q)
     {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -217,19 +262,26 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
         }
         use_request(q.slot);
         if (parked) {
-            q.pend = 0;
-            if (DIAG) this->p_hash = phash()[i];
+            load_parked_state(rec(k, i), q, cur_v, cur_e, k == WS_ELECTRON);
+            if (DIAG) this->p_hash = hashes(k)[i];
         } else {
             this->start_particle(q);
         }
         return true;
     }
 
-    // Parks the lane's photon (mid-flight) on the photon stack.
+    // Parks the lane's particle (mid-flight) on the stack of its kind with its
+    // open tally visit; the lane starts its next particle with none.
     DEV void park(Part& q)
     {
-        flush_particle(q);
-        push(WS_PHOTON, q, true, DIAG ? this->p_hash : 0ull);
+        if (DIAG && hist) {
+            mcd_history_record* r = &hist[q.h - first];
+            if (p_edep != 0.0) unsafeAtomicAdd(&r->edep, p_edep);
+            if (p_track != 0.0) unsafeAtomicAdd(&r->track_e, p_track);
+        }
+        p_edep = p_track = 0.0;
+        push(q.type == PHOTON ? WS_PHOTON : WS_ELECTRON, q, true, DIAG ? this->p_hash : 0ull);
+        cur_v = -1;
         q.type = DEAD;
     }
 
@@ -256,10 +308,10 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
     }
 
     // Fetch step of the lanes that need a particle: first the stack of the
-    // kind the wave mostly runs (electrons unless photons outnumber them),
-    // then the other stack, then new histories.  Returns false for a lane
-    // whose claim found the histories exhausted.
-    DEV bool fetch_wave(Part& q, bool prefer_photons)
+    // wave's mode, then new histories while they may start, else the other
+    // stack.  Returns false only for a lane whose claim found the histories
+    // exhausted (claims held back by full stacks are not exhaustion).
+    DEV bool fetch_wave(Part& q, bool prefer_photons, bool can_claim)
     {
         const uint64_t m = __builtin_amdgcn_ballot_w64(true);
         const unsigned rank =
@@ -267,7 +319,7 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
         const unsigned nfl = (unsigned)__popcll(m);
         const int ka = prefer_photons ? WS_PHOTON : WS_ELECTRON, kb = 1 - ka;
         const unsigned ca = cnt[ka], cb = cnt[kb];
-        const unsigned ta = min(nfl, ca), tb = min(nfl - ta, cb);
+        const unsigned ta = min(nfl, ca), tb = can_claim ? 0u : min(nfl - ta, cb);
         cnt[ka] = ca - ta;
         cnt[kb] = cb - tb;
         if (rank < ta) take(ka, ca - 1 - rank, q);
@@ -276,17 +328,17 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
         // push onto the slots just freed (a positron primary below its
         // cutoff annihilates at once)
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (rank < ta + tb) return true;
-        if (!more_new || this->failed) return false;
+        if (rank < ta + tb || !can_claim || this->failed) return true;
         return claim(q);
     }
 
     // ---------------------------------------------------- wave schedule
-    // As Transport::run, with the wave stacks: fetching lanes count only
-    // while a stack holds particles or new histories remain; before an
-    // electron step, photon lanes park their photons and take waiting
-    // electrons; the wave ends when no lane holds a particle and nothing is
-    // left to fetch.
+    // As Transport::run, with the wave stacks and the wave's mode (photon or
+    // electron): lanes holding the other kind park and take waiting particles
+    // of the mode's kind; fetching lanes count only while something can be
+    // fetched; steps of the mode's kind run unless fetch or hard-event
+    // thresholds call; the wave ends when no lane holds a particle and
+    // nothing is left to fetch.
     enum { ST_FETCH, ST_PHOTON, ST_ELECTRON, ST_HARD };
 
     DEV int state(const Part& q) const
@@ -294,40 +346,66 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
         return q.type == DEAD ? ST_FETCH : (q.type == PHOTON ? ST_PHOTON : (q.pend ? ST_HARD : ST_ELECTRON));
     }
 
+    // Lanes in state from1 or from2 (the first `top` of them) park their
+    // particle on its own kind's stack and take record top - 1 - rank of
+    // stack `to`, which holds the other kind; that stack keeps top - k.
+    DEV void swap_in(Part& q, int st, int from1, int from2, int to, unsigned top)
+    {
+        if (st == from1 || st == from2) {
+            const uint64_t m = __builtin_amdgcn_ballot_w64(true);
+            const unsigned rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            const unsigned k = min((unsigned)__popcll(m), top);
+            if (rank < k) {
+                park(q);
+                take(to, top - 1 - rank, q);
+            }
+            cnt[to] = top - k;
+        }
+    }
+
     DEV void run_wave(Part& q, const Sched sc)
     {
+        const unsigned claim_cap = min(cap() / 4u, 384u);
+        const int low = max(64 / sc.photon_div, 1);
+        const bool claim_photon = p.req[0].src.particle == PHOTON;
+        int mode = claim_photon ? ST_PHOTON : ST_ELECTRON;      // wave-uniform
         for (;;) {
             int st = state(q);
             const uint64_t live = __builtin_amdgcn_ballot_w64(true);
             const int n = __popcll(live);
-            const int nf = __popcll(__builtin_amdgcn_ballot_w64(st == ST_FETCH));
-            const int np = __popcll(__builtin_amdgcn_ballot_w64(st == ST_PHOTON));
-            const int nh = __popcll(__builtin_amdgcn_ballot_w64(st == ST_HARD));
-            const int ne = n - nf - np - nh;
+            int nf = __popcll(__builtin_amdgcn_ballot_w64(st == ST_FETCH));
+            int np = __popcll(__builtin_amdgcn_ballot_w64(st == ST_PHOTON));
+            int nh = __popcll(__builtin_amdgcn_ballot_w64(st == ST_HARD));
+            int ne = n - nf - np - nh;
             const unsigned sg = cnt[WS_PHOTON], se = cnt[WS_ELECTRON];
-            const bool avail = sg + se > 0 || more_new;
-            if (nf == n && !avail) break;
-            const int nfe = avail ? nf : 0;
+            if (nf == n && sg + se == 0 && !more_new) break;
+            const bool can_claim = more_new && sg + se < claim_cap;
+            // work of each kind: lanes, stacked particles, and fetching lanes
+            // when new histories (of the first source's kind) may start
+            const int wp = np + (int)min(sg, 64u) + (can_claim && claim_photon ? nf : 0);
+            const int we = ne + nh + (int)min(se, 64u) + (can_claim && !claim_photon ? nf : 0);
+            if (mode == ST_PHOTON ? (wp < low && we > wp) : (we < low && wp > we))
+                mode = ST_PHOTON + ST_ELECTRON - mode;
+            if (mode == ST_ELECTRON && np && se) {
+                swap_in(q, st, ST_PHOTON, ST_PHOTON, WS_ELECTRON, se);
+            } else if (mode == ST_PHOTON && ne + nh && sg) {
+                swap_in(q, st, ST_ELECTRON, ST_HARD, WS_PHOTON, sg);
+            }
+            st = state(q);
+            nf = __popcll(__builtin_amdgcn_ballot_w64(st == ST_FETCH));
+            np = __popcll(__builtin_amdgcn_ballot_w64(st == ST_PHOTON));
+            nh = __popcll(__builtin_amdgcn_ballot_w64(st == ST_HARD));
+            ne = n - nf - np - nh;
+            const bool fetchable = cnt[WS_PHOTON] + cnt[WS_ELECTRON] > 0 || can_claim;
+            const int nfe = fetchable ? nf : 0;
             int act;
             if (nfe && (nfe * sc.fetch_div >= n || nfe == n)) act = ST_FETCH;
             else if (nh && (nh * sc.hard_div >= n || nh + nf == n)) act = ST_HARD;
-            else if (np && np * sc.photon_div >= ne) act = ST_PHOTON;
+            else if (mode == ST_PHOTON ? np : ne) act = mode;
+            else if (np) act = ST_PHOTON;
             else if (ne) act = ST_ELECTRON;
             else act = nh ? ST_HARD : ST_FETCH;
-            if (act == ST_ELECTRON && np && se) {
-                if (st == ST_PHOTON) {
-                    const uint64_t m = __builtin_amdgcn_ballot_w64(true);
-                    const unsigned rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    const unsigned k = min((unsigned)__popcll(m), se);
-                    if (rank < k) {
-                        park(q);
-                        take(WS_ELECTRON, se - 1 - rank, q);
-                    }
-                    cnt[WS_ELECTRON] = se - k;
-                }
-                st = state(q);
-            }
             const int na = DIAG ? __popcll(__builtin_amdgcn_ballot_w64(st == act)) : 0;
             if (DIAG && __builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32),
                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0u)) == 0) {
@@ -339,7 +417,7 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
             bool exhausted = false;
             if (st == act) {
                 if (act == ST_FETCH) {
-                    exhausted = !fetch_wave(q, np > ne);
+                    exhausted = !fetch_wave(q, mode == ST_PHOTON, can_claim);
                 } else if (act == ST_PHOTON) {
                     this->photon_step(q);
                 } else if (act == ST_ELECTRON) {
@@ -380,11 +458,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     L.reduce_out(p.bal, p.cnt);
 }
 
-// Bytes of one wave's stacks for `cap` records per stack (photon records and
-// their diagnostic hashes, electron records).
+// Bytes of one wave's stacks for `cap` records per stack (photon and electron
+// records and their diagnostic event hashes).
 size_t wave_stack_bytes(int cap)
 {
-    const size_t b = (size_t)cap * (2 * kWaveRec + sizeof(uint64_t));
+    const size_t b = (size_t)cap * (kWaveRec + kWaveERec + 2 * sizeof(uint64_t));
     return (b + 255) & ~(size_t)255;
 }
 

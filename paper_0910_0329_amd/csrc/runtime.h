@@ -38,6 +38,12 @@ struct SchedDefaults {
 constexpr SchedDefaults kSchedPhotonSources{3, 24, 2};
 constexpr SchedDefaults kSchedChargedSources{4, 8, 6};
 constexpr SchedDefaults kSchedPlain{3, 24, 2};
+// Wave-stack schedule (the default regrouped one): fetch at 1/4 (photon
+// sources) or 1/6 of the lanes, hard events at 1/24 or 1/8; photon_div there
+// sets when the wave leaves its photon or electron mode (work of the mode's
+// kind below 64 / photon_div lanes): 1, as soon as it cannot fill the wave.
+constexpr SchedDefaults kSchedWavePhotonSources{4, 24, 1};
+constexpr SchedDefaults kSchedWaveChargedSources{6, 8, 1};
 
 // Small per-run device block: energy balance, counters, error flag, work
 // counter and finalisation reductions of the plain kernel.

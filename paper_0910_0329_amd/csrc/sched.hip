@@ -251,7 +251,7 @@ int mcd_ctx::prepare_regroup(int32_t phantom, const mcd_source* const* srcs, con
     plan.depth = opts && opts->stack_depth ? opts->stack_depth : kDefaultDepth;
     if (opts && (opts->regroup < 0 || opts->regroup > 3)) return fail(MCD_E_INVAL, "opts: regroup must be 0 to 3");
     plan.use_queues = opts && opts->regroup == 1;
-    plan.wave_stacks = opts && opts->regroup == 3;
+    plan.wave_stacks = !opts || opts->regroup == 0 || opts->regroup == 3;
     plan.fp32 = opts && opts->tally_fp32 ? 1 : 0;
     plan.diag = opts && opts->diagnostics;
     if (opts && (opts->refined_build < 0 || opts->refined_build > 1))
@@ -263,8 +263,9 @@ int mcd_ctx::prepare_regroup(int32_t phantom, const mcd_source* const* srcs, con
     if (rc) return rc;
     bool photons_only = true;
     for (int r = 0; r < n_req; ++r) photons_only = photons_only && srcs[r] && srcs[r]->particle == MCD_PHOTON;
-    if ((rc = wave_schedule(opts, &plan.sched, photons_only ? kSchedPhotonSources : kSchedChargedSources)))
-        return rc;
+    const SchedDefaults sd = plan.wave_stacks ? (photons_only ? kSchedWavePhotonSources : kSchedWaveChargedSources)
+                                              : (photons_only ? kSchedPhotonSources : kSchedChargedSources);
+    if ((rc = wave_schedule(opts, &plan.sched, sd))) return rc;
     plan.req.resize(n_req);
     plan.fin.resize(n_req);
     plan.nb.assign((size_t)n_req * kBatches, 0.0);

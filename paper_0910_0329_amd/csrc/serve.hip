@@ -162,7 +162,8 @@ static void admit(mcd_ctx* c, mcd_server* S)
         size_t reserve = (size_t)1 << 20;
         if (c->launch_shape(&S->cfg.opts, c->tables[ph.tables].n_mat, &blocks, &threads) == MCD_OK) {
             const uint64_t lanes = (uint64_t)blocks * threads;
-            const size_t lanes_b = stack_scratch_bytes(lanes, depth, S->cfg.opts.regroup == 3);
+            const size_t lanes_b =
+                stack_scratch_bytes(lanes, depth, S->cfg.opts.regroup == 0 || S->cfg.opts.regroup == 3);
             if (lanes_b > c->rb.scratch_bytes) reserve += lanes_b - c->rb.scratch_bytes;
             if (S->cfg.opts.regroup == 1) {
                 const int cpl = S->cfg.opts.chunk_per_lane ? S->cfg.opts.chunk_per_lane : kDefaultChunkPerLane;
