@@ -13,14 +13,21 @@ finalisation, scalar read-back) with phantom and tables resident in HBM.
 Alongside, in the same JSON line:
   forms       the plain per-history kernel at the same N_1%, the batched form
               (128 beamlets in one hipGraph launch with autotuned options vs
-              128 separate plain launches) and the served form (timed Poisson
-              arrivals through the serving loop: p50/p99 latency, histories/s);
+              128 separate plain and 128 separate regrouped launches) and the
+              served forms (timed Poisson arrivals through the serving loop:
+              p50/p99 latency, histories/s; fixed N and sigma-bar targets);
   electron    20 MeV electrons on the 32x32x30 water-lung-water phantom: the
               pencil beam at its N_1% and at 1e7 histories, and a 10x10 cm
               point-source field at its N_1%;
-  roofline    ALU roofline of the photon transport phase (algorithmic lane-ops
-              per history from the converged-path measurement);
-  cpu_baseline the FP64 oracle on a bounded sample of the headline workload.
+  roofline    ALU roofline of the transport kernel (algorithmic lane-ops per
+              history from the converged-path measurement), HBM traffic and
+              the FP64 atomic rate against measured ceilings;
+  table_variants, table_placement_tissues8, paper_geometry, end_to_end
+              physics-refinement tables, LDS vs global tables on an
+              eight-tissue CT, the paper's Table 1 setups, and the paper's T;
+  cpu_baseline, oracle_agreement
+              the FP64 oracle on a bounded sample of the headline and electron
+              workloads, and the GPU's dose on the same histories against it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -49,7 +56,7 @@ PATH_LANE_OPS = {
 # = 3.93e13 lane-ops/s (one non-packed FP32/INT32 op per lane per cycle).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # HBM bytes per history of the transport kernel (the wave-stack kernel
-# k_wave<false, false>): rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by
+# k_wave<false, false, false>): rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by
 # its reading for a 1 GiB device copy (profiles/transport_g6mv_hbm_traffic.md,
 # profiles/transport_e20_wlw_hbm_traffic.md).
 TRAFFIC_BYTES_PER_HIST = {
@@ -294,7 +301,7 @@ def main():
     }
 
     path = PATH_LANE_OPS.get(wg.name)
-    roofline = {"bound": "alu", "kernel": "k_wave<false,false> (wave-stack transport)", "achieved": None,
+    roofline = {"bound": "alu", "kernel": "k_wave<false,false,false> (wave-stack transport, LDS tables)", "achieved": None,
                 "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s", "frac": None, "traffic": None,
                 "per_launch_ms": k_ms / max(launches, 1), "histories_per_launch": n1 / max(launches, 1)}
     if path:
@@ -389,6 +396,31 @@ def main():
         variants[variant] = cur
     line["table_variants"] = variants
     log(f"table variants: {variants}")
+
+    # ------------------------------------------------------------ table placement
+    # eight tissue classes: the LDS copy of their tables (128 KiB) leaves room
+    # for one 512-thread workgroup per CU; device-memory tables (the automatic
+    # choice here) let the registers set the occupancy
+    from paper_0910_0329_amd.mcdose import TABLES_GLOBAL, TABLES_LDS
+    wt = configs.photon_6mv_ct8(40_000_000)
+    th8 = eng.load_materials(tables.tissue_blob())
+    p8 = eng.load_phantom(wt.phantom, th8)
+    placement = {"workload": f"{wt.name}: 6 MV, 10x10 cm field, 128^3 x 0.25 cm random field in 8 tissue classes",
+                 "histories": wt.n_histories}
+    for label, opts in (("lds", {"table_placement": TABLES_LDS}), ("global", {"table_placement": TABLES_GLOBAL}),
+                        ("auto", {})):
+        shape = eng.launch_shape(p8, **opts)
+        eng.simulate(p8, wt.source, wt.n_histories // 10, wt.seed, n_vox=wt.phantom.n_vox, **opts)
+        tp_, rp_ = timed(lambda: eng.simulate(p8, wt.source, wt.n_histories, wt.seed, n_vox=wt.phantom.n_vox,
+                                              **opts), 2)
+        placement[label] = {"hist_per_s": wt.n_histories / tp_,
+                            "kernel_hist_per_s": wt.n_histories / (rp_["kernel_ms"] * 1e-3),
+                            "waves_per_cu": shape["resident_per_cu"] * shape["block_size"] // 64,
+                            "table_placement": "global" if shape["table_placement"] == TABLES_GLOBAL else "lds"}
+    eng.unload_phantom(p8)
+    eng.unload_materials(th8)
+    line["table_placement_tissues8"] = placement
+    log(f"table placement, 8 tissues: {placement}")
 
     # ------------------------------------------------------------ paper geometry
     from paper_0910_0329_amd.inputs.sources import ELECTRON, PHOTON

@@ -133,6 +133,8 @@ typedef struct {
  *                         and an exact history-by-history local counter
  *                         (sigma from the per-history second moment).      */
 enum { MCD_KERNEL_REGROUPED = 0, MCD_KERNEL_PLAIN = 1 };
+/* mcd_opts.table_placement */
+enum { MCD_TABLES_AUTO = 0, MCD_TABLES_LDS = 1, MCD_TABLES_GLOBAL = 2 };
 
 /* Run options; NULL means defaults.  None of them changes which histories are
  * simulated or how: the histories depend only on (tables, phantom, source,
@@ -141,7 +143,9 @@ enum { MCD_KERNEL_REGROUPED = 0, MCD_KERNEL_PLAIN = 1 };
 typedef struct {
     uint64_t first_history;   /* histories [first_history, first_history + n) */
     int32_t block_size;       /* threads per block, 0 = tuned default */
-    int32_t grid_blocks;      /* blocks, 0 = enough to fill the device */
+    int32_t grid_blocks;      /* blocks, 0 = enough to fill the device (with the wave-stack
+                                 schedule: the number of workgroups the device holds at
+                                 once, from the kernel's registers and LDS) */
     int32_t stack_depth;      /* particle stack per lane, 0 = default (64) */
     int32_t tally_slots;      /* plain kernel: local counter slots (power of 2), 0 = 512 */
     int32_t diagnostics;      /* 1: fill counters (slower kernel variant) */
@@ -181,6 +185,17 @@ typedef struct {
     int32_t refined_build;    /* 1: run the transport kernels built with the refinement code
                                  even when the tables use none of it (the same histories;
                                  a check of the lean build).  0 = pick by the tables */
+    int32_t table_placement;  /* where the transport reads the photon and electron tables
+                                 (32 B per material and energy node, Sec. 2.3):
+                                 MCD_TABLES_LDS = a copy in each workgroup's LDS;
+                                 MCD_TABLES_GLOBAL = device memory, through the L1 and L2
+                                 caches, which leaves the LDS free (wave-stack schedule,
+                                 regroup 0 or 3, only; other schedules return MCD_E_INVAL);
+                                 MCD_TABLES_AUTO (0, default) = the LDS unless its copy lets
+                                 a CU hold fewer workgroups than device-memory tables do
+                                 (large table sets), then device memory; the other
+                                 schedules always use the LDS.  The histories are the same
+                                 either way. */
 } mcd_opts;
 
 /* Output of a run.  dose and sigma (nx*ny*nz doubles each, Gy per source
@@ -304,6 +319,18 @@ typedef struct {
  * n_items <= 4096; the sum of n_histories < 2^40. */
 int mcd_simulate_batch(mcd_ctx* ctx, int32_t phantom, const mcd_batch_item* items, int32_t n_items,
                        uint64_t seed, const mcd_opts* opts, mcd_result* total, void* hip_stream);
+
+/* The launch shape a run on `phantom` with `opts` (NULL = defaults) takes:
+ * workgroups (`*grid_blocks`, the default when opts->grid_blocks is 0) of
+ * `*block_size` threads, the device's compute units (`*cu_count`), the
+ * workgroups one CU holds at once for that kernel (`*resident_per_cu`, from
+ * its registers and LDS; the wave-stack kernel only, else 0) and the table
+ * placement MCD_TABLES_AUTO resolves to (`*table_placement`, LDS or GLOBAL).
+ * Options are validated as mcd_simulate does; nothing runs.  For tuning the
+ * occupancy (waves per CU) of a persistent launch. */
+int mcd_launch_shape(mcd_ctx* ctx, int32_t phantom, const mcd_opts* opts, int32_t* grid_blocks,
+                     int32_t* block_size, int32_t* cu_count, int32_t* resident_per_cu,
+                     int32_t* table_placement);
 
 /* ------------------------------------------------------------------ serving
  *

@@ -1,11 +1,16 @@
-"""Autotuner of the regrouped launch: picks the regrouping schedule, block
-shape and chunk size (which also sizes the particle queues: 3 x lanes x
-chunk_per_lane records), then the wave-schedule thresholds, for a workload by
-timing short batched runs on the device, and caches the choice per device and
-workload shape in a JSON file.
+"""Autotuner of the regrouped launch.  For a workload it times short batched
+runs on the device and picks, in three stages:
 
-The search times a scaled-down copy of the workload (every item's history
-count divided by `scale`, at least `min_hist`), so a tuning pass costs a few
+1. the regrouping schedule, block shape, table placement (LDS or device
+   memory, wave-stack schedule only) and chunk size (queues only; it also
+   sizes them: 3 x lanes x chunk_per_lane records);
+2. the occupancy of the winner: workgroups per CU (and so waves per CU) from
+   one up to the number the device holds at once, as grid_blocks;
+3. the wave-schedule thresholds.
+
+The choice is cached per device and workload shape in a JSON file.  The
+search times a scaled-down copy of the workload (every item's history count
+divided by `scale`, at least `min_hist`), so a tuning pass costs a few
 seconds; the result depends only on timing, never on the dose, because every
 option runs the same histories.
 """
@@ -18,15 +23,17 @@ import os
 import time
 
 DEFAULT_SPACE = {
-    "regroup": (1, 2),
+    "regroup": (1, 2, 3),
     "chunk_per_lane": (8, 16, 32, 64),
     "block_size": (256, 512),
+    "table_placement": (1, 2),          # MCD_TABLES_LDS, MCD_TABLES_GLOBAL
 }
-# second stage, searched around the best launch options
+# second stage, searched around the best launch options (with wave stacks,
+# regroup 3, photon_div sets the photon/electron mode switch)
 SCHED_SPACE = {
-    "sched_fetch_div": (3, 4),
+    "sched_fetch_div": (3, 4, 6),
     "sched_hard_div": (8, 24),
-    "sched_photon_div": (2, 6),
+    "sched_photon_div": (1, 2, 6),
 }
 CACHE_ENV = "MCDOSE_TUNE_CACHE"
 
@@ -67,15 +74,29 @@ def store_cache(key: str, entry: dict, path: str | None = None):
 
 
 def candidates(space=None):
-    """Every combination of the values in `space`; chunk_per_lane only matters
-    with queues (regroup 1), so lane-stack candidates keep its first value."""
+    """Every combination of the values in `space`, except that chunk_per_lane
+    only matters with queues (regroup 1) and table_placement only with wave
+    stacks (regroup 3): other schedules keep their first value."""
     space = space or DEFAULT_SPACE
     names = sorted(space)
     for combo in itertools.product(*(space[n] for n in names)):
         d = dict(zip(names, combo))
-        if d.get("regroup") == 2 and "chunk_per_lane" in space and d["chunk_per_lane"] != space["chunk_per_lane"][0]:
+        if d.get("regroup") in (2, 3) and "chunk_per_lane" in space and \
+                d["chunk_per_lane"] != space["chunk_per_lane"][0]:
+            continue
+        if d.get("regroup") in (1, 2) and "table_placement" in space and \
+                d["table_placement"] != space["table_placement"][0]:
             continue
         yield d
+
+
+def occupancy_candidates(shape: dict):
+    """grid_blocks for one up to one fewer than the workgroups a CU holds at
+    once (the default grid fills the device, so it is already timed), from
+    the launch shape of mcd_launch_shape; none for kernels without the
+    occupancy figure."""
+    per_cu = int(shape.get("resident_per_cu", 0))
+    return [{"grid_blocks": shape["cu_count"] * k} for k in range(1, per_cu)]
 
 
 def scaled(items, scale: int, min_hist: int):
@@ -83,13 +104,14 @@ def scaled(items, scale: int, min_hist: int):
 
 
 def tune(eng, phantom: int, n_vox: int, items, seed: int, *, space=None, sched_space=None,
-         scale: int = 8, min_hist: int = 2000, reps: int = 2, use_cache: bool = True,
-         path: str | None = None, device_name: str | None = None, log=None) -> dict:
+         occupancy: bool = True, scale: int = 8, min_hist: int = 2000, reps: int = 2,
+         use_cache: bool = True, path: str | None = None, device_name: str | None = None, log=None) -> dict:
     """Returns the fastest launch options for `items` (sequence of (source,
     n_histories, request_key)) on `phantom`, from the cache when present.
-    Stage 1 searches `space` (launch shape and regrouping); stage 2 searches
-    `sched_space` (wave-schedule thresholds) with the stage-1 winner; an
-    empty `sched_space` ({}) skips stage 2."""
+    Stage 1 searches `space` (regrouping, block shape, table placement);
+    stage 2 the workgroups per CU of the stage-1 winner (`occupancy`);
+    stage 3 `sched_space` (wave-schedule thresholds) around the best so far;
+    an empty `sched_space` ({}) skips stage 3."""
     import torch
 
     if device_name is None:
@@ -111,6 +133,13 @@ def tune(eng, phantom: int, n_vox: int, items, seed: int, *, space=None, sched_s
     if not results:
         raise RuntimeError("autotune: no candidate ran")
     results.sort(key=lambda t: t[0])
+    if occupancy:
+        base = results[0][1]
+        for extra in occupancy_candidates(eng.launch_shape(phantom, **base)):
+            r = _time(eng, phantom, n_vox, probe, n_probe, seed, {**base, **extra}, reps, log)
+            if r:
+                results.append(r)
+        results.sort(key=lambda t: t[0])
     if stage2:
         base = results[0][1]
         for extra in candidates(stage2):

@@ -24,13 +24,15 @@ HIPCC_FLAGS = [
 ]
 
 
-# Production (non-diagnostic) transport kernels: checked for private scratch.
-# the production (no-diagnostics) transport kernels, with and without the
-# refinement code: k_plain<false, REF>, k_phase<false, PHOTONS, REF>
+# The production (no-diagnostics) transport kernels, checked for private
+# scratch: with and without the refinement code, k_plain<false, REF>,
+# k_phase<false, PHOTONS, REF>, and k_wave<false, REF, GTAB> for both table
+# placements.  Every name must be found in the build.
 HOT_KERNELS = ("_ZN3mcd7k_plainILb0ELb0EEEvNS_6KPlainE", "_ZN3mcd7k_plainILb0ELb1EEEvNS_6KPlainE",
                "_ZN3mcd7k_phaseILb0ELb0ELb0EEEvNS_6KPhaseE", "_ZN3mcd7k_phaseILb0ELb0ELb1EEEvNS_6KPhaseE",
                "_ZN3mcd7k_phaseILb0ELb1ELb0EEEvNS_6KPhaseE", "_ZN3mcd7k_phaseILb0ELb1ELb1EEEvNS_6KPhaseE",
-               "_ZN3mcd6k_waveILb0ELb0EEEvNS_6KPhaseE", "_ZN3mcd6k_waveILb0ELb1EEEvNS_6KPhaseE")
+               "_ZN3mcd6k_waveILb0ELb0ELb0EEEvNS_6KPhaseE", "_ZN3mcd6k_waveILb0ELb1ELb0EEEvNS_6KPhaseE",
+               "_ZN3mcd6k_waveILb0ELb0ELb1EEEvNS_6KPhaseE", "_ZN3mcd6k_waveILb0ELb1ELb1EEEvNS_6KPhaseE")
 
 
 def resource_usage(asm: str) -> dict:
@@ -72,6 +74,7 @@ def build(verbose: bool = False) -> str:
     """Compiles every HIP source and links the shared library; returns its path."""
     objdir = os.path.join(ROOT, "_build")
     os.makedirs(objdir, exist_ok=True)
+    found = set()
 
     def compile_one(src):
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
@@ -85,6 +88,7 @@ def build(verbose: bool = False) -> str:
             asm = f.read()
         usage = resource_usage(asm)
         priv = scratch_instructions(asm)
+        found.update(k for k in HOT_KERNELS if k in usage)
         if verbose:
             for k, v in usage.items():
                 print(k, v, "scratch instructions:", priv.get(k, 0), file=sys.stderr)
@@ -99,6 +103,9 @@ def build(verbose: bool = False) -> str:
 
     with ThreadPoolExecutor(len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
+    missing = set(HOT_KERNELS) - found
+    if missing:
+        raise RuntimeError(f"production kernels not in the build: {sorted(missing)}")
     tmp = LIB + ".tmp"
     r = subprocess.run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp],
                        capture_output=True, text=True)

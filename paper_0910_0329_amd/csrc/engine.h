@@ -144,7 +144,12 @@ int transport_lds_bytes(int n_mat);
 hipError_t launch_plain(const KPlain& p, int blocks, int threads, bool diag, hipStream_t s);
 hipError_t launch_phase(const KPhase& p, bool photons, int blocks, int threads, bool diag,
                         hipStream_t s);
-hipError_t launch_wave(const KPhase& p, int blocks, int threads, bool diag, hipStream_t s);
+// gtab: photon and electron tables read from device memory, not LDS.
+hipError_t launch_wave(const KPhase& p, int blocks, int threads, bool diag, bool gtab, hipStream_t s);
+// LDS bytes per workgroup of the wave-stack kernel, and the workgroups of
+// `threads` threads one CU holds at once (registers and LDS; 0 on error).
+int wave_lds_bytes(int n_mat, bool gtab);
+int wave_blocks_per_cu(int threads, int n_mat, bool gtab);
 hipError_t launch_finalize(const double* S, const double* Q, const uint2* vox, int64_t nv,
                            double vol, uint64_t n, double* dose, double* sigma, double* red,
                            hipStream_t s);

@@ -432,13 +432,14 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
     }
 };
 
-template <bool DIAG, bool REF>
+// GTAB: photon and electron tables read from device memory instead of LDS.
+template <bool DIAG, bool REF, bool GTAB>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_wave(KPhase p)
 {
     extern __shared__ float4 lds[];
     Env env;
     float* extra;
-    stage_tables(p.g, lds, env, &extra);
+    stage_tables<GTAB>(p.g, lds, env, &extra);
     // wave-uniform: the wave's index, its LDS counters and its stacks
     const uint32_t w_in_block = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     volatile unsigned int* wc = (volatile unsigned int*)extra + 2 * w_in_block;
@@ -469,24 +470,46 @@ size_t wave_stack_bytes(int cap)
 static void (*wave_kernel(int which))(KPhase)
 {
     switch (which) {
-    case 0: return k_wave<false, false>;
-    case 1: return k_wave<false, true>;
-    case 2: return k_wave<true, false>;
-    default: return k_wave<true, true>;
+    case 0: return k_wave<false, false, false>;
+    case 1: return k_wave<false, true, false>;
+    case 2: return k_wave<true, false, false>;
+    case 3: return k_wave<true, true, false>;
+    case 4: return k_wave<false, false, true>;
+    case 5: return k_wave<false, true, true>;
+    case 6: return k_wave<true, false, true>;
+    default: return k_wave<true, true, true>;
     }
 }
 
-hipError_t launch_wave(const KPhase& p, int blocks, int threads, bool diag, hipStream_t s)
+static int wave_which(bool diag, bool refined, bool gtab)
 {
-    const size_t lds = transport_lds_bytes(p.g.t.n_mat);
-    const int which = (diag ? 2 : 0) | (p.g.t.refined ? 1 : 0);
-    hipLaunchKernelGGL(wave_kernel(which), dim3(blocks), dim3(threads), lds, s, p);
+    return (gtab ? 4 : 0) | (diag ? 2 : 0) | (refined ? 1 : 0);
+}
+
+int wave_lds_bytes(int n_mat, bool gtab)
+{
+    return gtab ? transport_lds_bytes(0) : transport_lds_bytes(n_mat);
+}
+
+hipError_t launch_wave(const KPhase& p, int blocks, int threads, bool diag, bool gtab, hipStream_t s)
+{
+    const size_t lds = wave_lds_bytes(p.g.t.n_mat, gtab);
+    hipLaunchKernelGGL(wave_kernel(wave_which(diag, p.g.t.refined != 0, gtab)), dim3(blocks), dim3(threads),
+                       lds, s, p);
     return hipGetLastError();
+}
+
+int wave_blocks_per_cu(int threads, int n_mat, bool gtab)
+{
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, wave_kernel(wave_which(false, false, gtab)), threads, (size_t)wave_lds_bytes(n_mat, gtab));
+    return e == hipSuccess ? n : 0;
 }
 
 hipError_t init_wave_kernels(int max_lds)
 {
-    for (int which = 0; which < 4; ++which) {
+    for (int which = 0; which < 8; ++which) {
         const hipError_t e = hipFuncSetAttribute((const void*)wave_kernel(which),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
         if (e != hipSuccess) return e;

@@ -125,6 +125,7 @@ struct RegroupPlan {
     bool refined_build = false;      // force the kernels built with the refinement code
     bool use_queues = false;
     bool wave_stacks = false;        // secondaries on per-wave photon and electron stacks
+    bool global_tables = false;      // wave-stack kernel reads its tables from device memory
     Sched sched{};
     RegroupBufs* bufs = nullptr;     // device buffers the run uses (the context's, or a
     unsigned char* small = nullptr;  // carve-out of the no-allocation scratch)
@@ -254,7 +255,11 @@ struct mcd_ctx {
     int ensure_scratch(size_t lanes, int depth, int slots, hipStream_t s);
     int ensure_tallies(int64_t nv, hipStream_t s);
     int ensure_stage(int64_t nv, hipStream_t s);
-    int launch_shape(const mcd_opts* o, int n_mat, int* blocks, int* threads);
+    // Validates the launch options and resolves the default grid; gtab: the
+    // wave-stack kernel reads its tables from device memory; resident: the
+    // workgroups a CU holds at once (wave-stack kernel only, else 0).
+    int launch_shape(const mcd_opts* o, int n_mat, int* blocks, int* threads, bool* gtab = nullptr,
+                     int* resident = nullptr);
     int wave_schedule(const mcd_opts* o, mcd::Sched* sc, mcd::SchedDefaults d);
     void fill_geom(mcd::KGeom& g, const mcd::PhantomRec& ph);
     int simulate_plain(int32_t phantom, const mcd_source* src, uint64_t n, uint64_t seed,

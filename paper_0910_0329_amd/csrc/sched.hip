@@ -17,24 +17,66 @@ using namespace mcd;
 
 // ------------------------------------------------------------------ common
 
-int mcd_ctx::launch_shape(const mcd_opts* o, int n_mat, int* blocks, int* threads)
+int mcd_ctx::launch_shape(const mcd_opts* o, int n_mat, int* blocks, int* threads, bool* gtab_out,
+                          int* resident_out)
 {
     int t = o && o->block_size ? o->block_size : kDefaultBlock;
     if (t < 64 || t > 512 || (t & 63))
         return fail(MCD_E_INVAL, "opts: block_size must be a multiple of 64 in [64, 512]");
     int b = o && o->grid_blocks ? o->grid_blocks : 0;
     if (b < 0 || b > 1 << 20) return fail(MCD_E_INVAL, "opts: grid_blocks must be in [0, 2^20]");
-    const int lds = transport_lds_bytes(n_mat);
+    const int place = o ? o->table_placement : MCD_TABLES_AUTO;
+    if (place < MCD_TABLES_AUTO || place > MCD_TABLES_GLOBAL)
+        return fail(MCD_E_INVAL, "opts: table_placement must be MCD_TABLES_AUTO, _LDS or _GLOBAL");
+    // the wave-stack schedule of the regrouped kernel (regroup 0 or 3)
+    const bool wave = (!o || o->kernel == MCD_KERNEL_REGROUPED) && (!o || o->regroup == 0 || o->regroup == 3);
+    if (place == MCD_TABLES_GLOBAL && !wave)
+        return fail(MCD_E_INVAL, "opts: table_placement MCD_TABLES_GLOBAL needs the wave-stack schedule "
+                                 "(regrouped kernel, regroup 0 or 3)");
+    bool gtab = place == MCD_TABLES_GLOBAL;
+    // workgroups a CU holds at once: for the wave-stack kernel from its
+    // registers and LDS (either table placement), else from the LDS alone
+    int per_cu = 0;
+    if (wave) {
+        mcd::DeviceGuard dg(device);
+        const int in_lds = transport_lds_bytes(n_mat) <= max_lds ? wave_blocks_per_cu(t, n_mat, false) : 0;
+        const int in_mem = wave_blocks_per_cu(t, n_mat, true);
+        // automatic: device-memory tables only where the LDS copy costs workgroups
+        if (place == MCD_TABLES_AUTO) gtab = in_mem > in_lds;
+        per_cu = gtab ? in_mem : in_lds;
+    }
+    const int lds = wave ? wave_lds_bytes(n_mat, gtab) : transport_lds_bytes(n_mat);
     if (lds > max_lds)
         return fail(MCD_E_INVAL, "tables need " + std::to_string(lds) +
                                      " bytes of LDS per workgroup; the device allows " +
                                      std::to_string(max_lds));
-    if (b == 0) {
-        const int per_cu = std::max(1, std::min(kLdsPerCu / lds, 2048 / t));
-        b = cu_count * per_cu;
-    }
+    if (b == 0) b = cu_count * (per_cu > 0 ? per_cu : std::max(1, std::min(kLdsPerCu / lds, 2048 / t)));
     *blocks = b;
     *threads = t;
+    if (gtab_out) *gtab_out = gtab;
+    if (resident_out) *resident_out = per_cu;
+    return MCD_OK;
+}
+
+int mcd_launch_shape(mcd_ctx* c, int32_t phantom, const mcd_opts* opts, int32_t* grid_blocks,
+                     int32_t* block_size, int32_t* cu_count, int32_t* resident_per_cu,
+                     int32_t* table_placement)
+{
+    if (!c) return MCD_E_INVAL;
+    if (!grid_blocks || !block_size || !cu_count || !resident_per_cu || !table_placement)
+        return c->fail(MCD_E_INVAL, "launch_shape: null output");
+    std::lock_guard<mcd::FairMutex> run_lock(c->run_mu);
+    if (phantom < 0 || phantom >= (int32_t)c->phantoms.size() || !c->phantoms[phantom].live)
+        return c->fail(MCD_E_NOTFOUND, "unknown phantom handle");
+    int b = 0, t = 0, per_cu = 0;
+    bool gtab = false;
+    const int rc = c->launch_shape(opts, c->tables[c->phantoms[phantom].tables].n_mat, &b, &t, &gtab, &per_cu);
+    if (rc) return rc;
+    *grid_blocks = b;
+    *block_size = t;
+    *cu_count = c->cu_count;
+    *resident_per_cu = per_cu;
+    *table_placement = gtab ? MCD_TABLES_GLOBAL : MCD_TABLES_LDS;
     return MCD_OK;
 }
 
@@ -259,7 +301,7 @@ int mcd_ctx::prepare_regroup(int32_t phantom, const mcd_source* const* srcs, con
     plan.refined_build = opts && opts->refined_build;
     if (opts && opts->history_records && (!plan.diag || n_req != 1))
         return fail(MCD_E_INVAL, "history records need diagnostics and a single request");
-    int rc = launch_shape(opts, tables[ph.tables].n_mat, &plan.blocks, &plan.threads);
+    int rc = launch_shape(opts, tables[ph.tables].n_mat, &plan.blocks, &plan.threads, &plan.global_tables);
     if (rc) return rc;
     bool photons_only = true;
     for (int r = 0; r < n_req; ++r) photons_only = photons_only && srcs[r] && srcs[r]->particle == MCD_PHOTON;
@@ -426,7 +468,7 @@ int mcd_ctx::enqueue_cycles(const RegroupPlan& plan, int c0, int c1, hipStream_t
             // one launch takes every history; its waves pool their stacks
             k.stack_depth = 16 * plan.depth;
             k.lane_bytes = wave_stack_bytes(k.stack_depth);
-            hipError_t e = launch_wave(k, plan.blocks, plan.threads, plan.diag, s);
+            hipError_t e = launch_wave(k, plan.blocks, plan.threads, plan.diag, plan.global_tables, s);
             if (e != hipSuccess) return hip_fail(e, "wave-stack transport launch");
             continue;
         }
@@ -604,6 +646,7 @@ int mcd::run_regroup(mcd_ctx* c, RegroupPlan& plan, bool clear_tally, bool use_g
         add(&plan.refined_build, sizeof plan.refined_build);
         add(&plan.use_queues, sizeof plan.use_queues);
         add(&plan.wave_stacks, sizeof plan.wave_stacks);
+        add(&plan.global_tables, sizeof plan.global_tables);
         add(&plan.sched, sizeof plan.sched);
         add(&clear_tally, sizeof clear_tally);
         add(&c->rb, sizeof c->rb);

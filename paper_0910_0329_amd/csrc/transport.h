@@ -276,13 +276,29 @@ struct Transport {
         return invert_range([&](int j) { return env.elec[m * kNE + j].x; }, r, i0);
     }
 
-    // The node interval holding r is found by walking down from interval i0
-    // (r does not exceed the range at the start of the segment), then that
-    // linear piece is solved for log E.
+    // The node interval holding r (the last node j <= i0 with R_j <= r; r does
+    // not exceed the range at the start of the segment) is found by a fixed
+    // four-step binary search over the 16 nodes from i0 down: a segment loses
+    // at most the fraction f_E of its energy, under 12 nodes of the grid, so
+    // every lane takes the same four steps instead of a walk of its own
+    // length.  A range below that window (only the verification entry point
+    // asks for one) is walked down to.  Then that linear piece is solved for
+    // log E.
     template <class F> DEV float invert_range(F rnode, float r, int i0) const
     {
-        int j = i0;
+        int j = max(i0 - 15, 0);
         float rj = rnode(j);
+        if (rj <= r) {
+#pragma unroll
+            for (int step = 8; step > 0; step >>= 1) {
+                const int k = min(j + step, i0);
+                const float rk = rnode(k);
+                if (rk <= r) {
+                    j = k;
+                    rj = rk;
+                }
+            }
+        }
         while (j > 0 && rj > r) rj = rnode(--j);
         if (rj > r) return G().t.emin;
         float rn = rnode(j + 1);
@@ -1038,9 +1054,12 @@ struct Transport {
 
 // Stages the material tables and the majorant into LDS (dynamic shared memory
 // laid out as phot | elec | maj | r_abs | ray_b | r_abs_pos | extra floats).
+// GTAB: the photon and electron tables stay in device memory (read through
+// L1/L2); only the majorant and the per-material scalars go to LDS.
+template <bool GTAB = false>
 DEV void stage_tables(const KGeom& g, float4* lds, Env& env, float** extra)
 {
-    const int nt = g.t.n_mat * kNE;
+    const int nt = GTAB ? 0 : g.t.n_mat * kNE;
     float4* s_phot = lds;
     float4* s_elec = lds + nt;
     float* s_maj = (float*)(lds + 2 * nt);
@@ -1057,8 +1076,8 @@ DEV void stage_tables(const KGeom& g, float4* lds, Env& env, float** extra)
         s_rayb[i] = g.t.ray_b[i];
         s_rabp[i] = g.t.r_abs_pos[i];
     }
-    env.phot = s_phot;
-    env.elec = s_elec;
+    env.phot = GTAB ? g.t.phot : s_phot;
+    env.elec = GTAB ? g.t.elec : s_elec;
     env.maj = s_maj;
     env.r_abs = s_rabs;
     env.ray_b = s_rayb;

@@ -46,6 +46,16 @@ def photon_6mv_random_field(n: int = 100_000_000) -> Workload:
     return Workload("g6mv_rf_256x256x160", ph, src, n, 3)
 
 
+def photon_6mv_ct8(n: int = 40_000_000) -> Workload:
+    """6 MV as above on a 128^3 random-field phantom of 0.25 cm voxels (field
+    seed 52) mapped to the eight tissue classes (tissue_blob tables); seed 7."""
+    ph = phantoms.random_field_phantom(128, 0.25, seed=52)
+    ph.mat = phantoms.tissue_from_density(ph.rho)
+    x, y = ph.centre_xy()
+    src = sources.point_field(PHOTON, x, y, 100.0, 5.0, 5.0, spectrum=sources.spectrum_6mv())
+    return Workload("g6mv_ct8_128", ph, src, n, 7)
+
+
 def electron_20mev_point_field(ph, n: int) -> Workload:
     """20 MeV electrons from a point source at SSD 100 cm with a 10x10 cm field."""
     x, y = ph.centre_xy()

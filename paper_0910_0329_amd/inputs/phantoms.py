@@ -88,6 +88,18 @@ def material_from_density(rho: np.ndarray) -> np.ndarray:
     return mat
 
 
+# upper density bounds (g/cm^3) of the eight tissue classes, in the order
+# air, lung, adipose, water, muscle, cartilage, spongiosa (bone above)
+TISSUE_BOUNDS = (0.1, 0.5, 0.97, 1.02, 1.08, 1.14, 1.3)
+
+
+def tissue_from_density(rho: np.ndarray) -> np.ndarray:
+    """Eight-class material map for the TISSUES8 table set (material indices
+    0-3 air, lung, water, bone; 4-7 adipose, muscle, cartilage, spongiosa)."""
+    order = np.array([0, 1, 4, 2, 5, 6, 7, 3], dtype=np.uint8)
+    return order[np.digitize(rho, TISSUE_BOUNDS)]
+
+
 def random_field_phantom(n, d, seed, nz=None, sigma_cm=1.0) -> Phantom:
     """CT-like heterogeneous phantom from a Gaussian-smoothed random field.
 

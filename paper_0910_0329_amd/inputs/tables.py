@@ -108,6 +108,30 @@ MATERIALS = (
 )
 MAT_AIR, MAT_LUNG, MAT_WATER, MAT_BONE = range(4)
 
+
+def water_bone_mixture(name: str, rho: float, w_bone: float) -> Material:
+    """Effective atom of a mass fraction w_bone of bone in water: the per-gram
+    sums (Z/A, B, Z(Z+1)/A, P) add by mass fraction, and ln I by Bragg's
+    additivity rule, weighted by each part's electrons per gram."""
+    a, b = MATERIALS[MAT_WATER], MATERIALS[MAT_BONE]
+    wa = 1.0 - w_bone
+
+    def lin(x, y):
+        return wa * x + w_bone * y
+    zoa = lin(a.zoa, b.zoa)
+    ln_i = (wa * a.zoa * math.log(a.i_ev) + w_bone * b.zoa * math.log(b.i_ev)) / zoa
+    return Material(name, rho, zoa, math.exp(ln_i), lin(a.b, b.b), lin(a.ee, b.ee), lin(a.p, b.p))
+
+
+# Eight tissue classes of a CT-derived phantom: the four materials above plus
+# adipose and muscle (water's atom at their densities), cartilage and
+# spongiosa (10% and 40% of bone in water).  Eight materials is the most the
+# device holds per table set; their tables (128 KiB in FP32) no longer leave
+# room for two copies in a CU's LDS.
+TISSUES8 = MATERIALS + (water_bone_mixture("adipose", 0.95, 0.0), water_bone_mixture("muscle", 1.05, 0.0),
+                        water_bone_mixture("cartilage", 1.10, 0.1), water_bone_mixture("spongiosa", 1.18, 0.4))
+MAT_ADIPOSE, MAT_MUSCLE, MAT_CARTILAGE, MAT_SPONGIOSA = range(4, 8)
+
 # Elemental compositions (Z, A in g/mol, mass fraction) behind the effective
 # atoms above, used where a quantity is summed element by element.  Air is
 # dry air near sea level and water is H2O (their sums reproduce the effective
@@ -587,4 +611,12 @@ def standard_blob(variant: str = "standard", kappa_step: float = KAPPA_STEP) -> 
     key = (variant, kappa_step)
     if key not in _CACHE:
         _CACHE[key] = build_tables(variant=variant, kappa_step=kappa_step).to_blob()
+    return _CACHE[key]
+
+
+def tissue_blob() -> bytes:
+    """The standard blob for the eight tissue classes TISSUES8 (memoised)."""
+    key = ("tissues8",)
+    if key not in _CACHE:
+        _CACHE[key] = build_tables(materials=TISSUES8).to_blob()
     return _CACHE[key]

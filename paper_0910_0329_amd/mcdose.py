@@ -57,10 +57,12 @@ class Opts(C.Structure):
                 ("lockstep", C.c_int32), ("kernel", C.c_int32), ("tally_fp32", C.c_int32),
                 ("chunk_per_lane", C.c_int32), ("use_graph", C.c_int32), ("regroup", C.c_int32),
                 ("sched_fetch_div", C.c_int32), ("sched_hard_div", C.c_int32),
-                ("sched_photon_div", C.c_int32), ("refined_build", C.c_int32)]
+                ("sched_photon_div", C.c_int32), ("refined_build", C.c_int32),
+                ("table_placement", C.c_int32)]
 
 
 KERNEL_REGROUPED, KERNEL_PLAIN = 0, 1
+TABLES_AUTO, TABLES_LDS, TABLES_GLOBAL = 0, 1, 2          # mcd_opts.table_placement
 
 
 class Result(C.Structure):
@@ -136,6 +138,8 @@ def lib():
                                            C.POINTER(Opts), C.POINTER(Result), vp]
         L.mcd_measure_atomics.argtypes = [vp, vp, C.c_uint64, vp, C.c_uint64, i32, C.POINTER(C.c_double), vp]
         L.mcd_check_philox.argtypes = [vp, C.c_uint32, C.c_uint32, vp, C.c_uint64, vp, vp]
+        pi32 = C.POINTER(C.c_int32)
+        L.mcd_launch_shape.argtypes = [vp, i32, C.POINTER(Opts), pi32, pi32, pi32, pi32, pi32]
         L.mcd_check_tables.argtypes = [vp, i32, i32, i32, vp, C.c_uint64, vp, vp]
         L.mcd_status_string.argtypes = [C.c_int]
         L.mcd_status_string.restype = C.c_char_p
@@ -148,8 +152,8 @@ def lib():
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_load_materials", "mcd_unload_materials",
             "mcd_load_phantom", "mcd_unload_phantom", "mcd_simulate", "mcd_simulate_noalloc", "mcd_simulate_batch",
             "mcd_serve_configure", "mcd_submit", "mcd_submit_adaptive", "mcd_poll", "mcd_wait", "mcd_cancel",
-            "mcd_serve_stats_get", "mcd_check_philox", "mcd_check_tables", "mcd_measure_atomics", "mcd_status_string",
-            "mcd_last_error")
+            "mcd_serve_stats_get", "mcd_check_philox", "mcd_check_tables", "mcd_measure_atomics", "mcd_launch_shape",
+            "mcd_status_string", "mcd_last_error")
 
 # Quantities of mcd_check_tables (include/mcdose.h).
 Q_MU_C, Q_MU_PE, Q_MU_PP, Q_RANGE, Q_LAMBDA1_INV, Q_SIGMA_M, Q_SIGMA_B = range(7)
@@ -359,6 +363,18 @@ class Engine:
         self._check(lib().mcd_check_tables(self._h, phantom, material, quantity, xs.data_ptr(), xs.numel(),
                                            out.data_ptr(), _stream_ptr(stream)), "mcd_check_tables")
         return out
+
+    def launch_shape(self, phantom: int, **opts) -> dict:
+        """mcd_launch_shape: the launch a run with these options takes
+        (grid_blocks, block_size), the CU count, the workgroups one CU holds
+        at once (wave-stack kernel; 0 for the others) and the table placement
+        (TABLES_LDS or TABLES_GLOBAL) that TABLES_AUTO resolves to."""
+        o = make_opts(**opts)
+        v = [C.c_int32() for _ in range(5)]
+        self._check(lib().mcd_launch_shape(self._h, phantom, C.byref(o), *(C.byref(x) for x in v)),
+                    "mcd_launch_shape")
+        return dict(zip(("grid_blocks", "block_size", "cu_count", "resident_per_cu", "table_placement"),
+                        (x.value for x in v)))
 
     def measure_atomics(self, target, idx, reps: int = 1, stream=None) -> float:
         """Device milliseconds for reps x idx.numel() FP64 atomic adds at

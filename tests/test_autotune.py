@@ -12,9 +12,21 @@ def items():
 
 def test_candidates_cover_the_space():
     c = list(autotune.candidates())
-    assert len(c) == (4 + 1) * 2          # chunk sizes only with queues (regroup 1)
+    # chunk sizes only with queues (regroup 1), table placement only with wave stacks (3)
+    assert len(c) == (4 + 1 + 2) * 2
     assert len({tuple(sorted(d.items())) for d in c}) == len(c)
-    assert {"regroup", "chunk_per_lane", "block_size"} == set(c[0])
+    assert {"regroup", "chunk_per_lane", "block_size", "table_placement"} == set(c[0])
+    assert all(d["table_placement"] == 1 for d in c if d["regroup"] != 3)
+    assert {d["table_placement"] for d in c if d["regroup"] == 3} == {1, 2}
+    assert all(d["chunk_per_lane"] == 8 for d in c if d["regroup"] != 1)
+
+
+def test_occupancy_candidates_below_the_resident_count():
+    shape = {"grid_blocks": 512, "block_size": 512, "cu_count": 256, "resident_per_cu": 4}
+    assert autotune.occupancy_candidates(shape) == [{"grid_blocks": 256}, {"grid_blocks": 512},
+                                                   {"grid_blocks": 768}]
+    assert autotune.occupancy_candidates({**shape, "resident_per_cu": 0}) == []
+    assert autotune.occupancy_candidates({**shape, "resident_per_cu": 1}) == []
 
 
 def test_workload_key_depends_on_shape_and_mix():

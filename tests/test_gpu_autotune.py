@@ -22,12 +22,20 @@ def test_tune_and_reuse(blob, tmp_path):
         srcs, ns = sources.beamlets(w.phantom, seed=4)
         items = [(s, int(n) // 50 + 100, i) for i, (s, n) in enumerate(zip(srcs[:16], ns[:16]))]
         path = str(tmp_path / "tune.json")
-        space = {"regroup": (1, 2), "chunk_per_lane": (16, 64), "block_size": (512,)}
+        space = {"regroup": (1, 2, 3), "chunk_per_lane": (16, 64), "block_size": (256, 512),
+                 "table_placement": (1, 2)}
         sched = {"sched_fetch_div": (3, 4), "sched_hard_div": (16,), "sched_photon_div": (4,)}
         opts = autotune.tune(eng, pid, w.phantom.n_vox, items, 4, space=space, sched_space=sched, scale=1,
                              reps=1, path=path, log=print)
-        launch = {k: v for k, v in opts.items() if not k.startswith("sched_")}
+        launch = {k: v for k, v in opts.items() if not k.startswith("sched_") and k != "grid_blocks"}
         assert launch in list(autotune.candidates(space))
+        if "grid_blocks" in opts:
+            shape = eng.launch_shape(pid, **launch)
+            assert {"grid_blocks": opts["grid_blocks"]} in autotune.occupancy_candidates(shape)
+        table = autotune.load_cache(path)
+        tried = [t["opts"] for e in table.values() for t in e["table"]]
+        # every stage-1 candidate ran, and the occupancy stage ran when the winner had one
+        assert len(tried) >= len(list(autotune.candidates(space))) + len(sched["sched_fetch_div"])
         assert autotune.load_cache(path)
         again = autotune.tune(eng, pid, w.phantom.n_vox, items, 4, space=space, path=path)
         assert again == opts

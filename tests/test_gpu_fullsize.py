@@ -196,7 +196,7 @@ def test_ct_phantom_against_oracle_per_class(eng, blob, ct):
         r = ref["hist"]
         same = (rec["hash"] == r["hash"]) & np.isclose(rec["edep"], r["edep"], rtol=1e-3, atol=1e-6)
         log(f"  fp32={tally_fp32} history match fraction {same.mean():.4f}")
-        assert same.mean() > 0.98
+        assert same.mean() > 0.98              # measured 0.9973
         d = g["dose"].cpu().numpy()
         s = g["sigma"].cpu().numpy()
         sel = d_ref > 0.1 * dmax_ref
@@ -211,5 +211,5 @@ def test_ct_phantom_against_oracle_per_class(eng, blob, ct):
                 f"{ok[c].mean():.4f}, within 0.5 sigma {close[c].mean():.4f}, "
                 f"max |D - D_oracle| / Dmax {diff[c].max() / dmax_ref:.2e}")
             assert ok[c].all()
-            assert close[c].mean() > 0.9
+            assert close[c].mean() > 0.99      # measured 0.9991 (air) to 1.0000
         assert g["bal"]["E_src"] == pytest.approx(ref["bal"]["E_src"], rel=1e-6)

@@ -373,6 +373,91 @@ def test_kernels_agree_on_histories(eng, blob, th):
         assert np.max(np.abs(Sa[sel] - Sb[sel]) / Sa[sel]) < 5e-3
 
 
+@pytest.mark.parametrize("variant", ("standard", "refined", "tissues8"))
+@pytest.mark.parametrize("particle", [PHOTON, ELECTRON])
+def test_global_tables_run_the_same_histories(eng, variant, particle):
+    """The wave-stack kernel reading its photon and electron tables from
+    device memory (table_placement MCD_TABLES_GLOBAL) instead of LDS reads the
+    same FP32 values, so it runs the same histories: event hashes and
+    deposits agree history by history, and the tallies to summation order.
+    With the eight-tissue table set the automatic placement picks device
+    memory (the LDS copy leaves room for fewer workgroups)."""
+    import torch
+    from paper_0910_0329_amd.inputs import tables as T
+    from paper_0910_0329_amd.mcdose import TABLES_GLOBAL, TABLES_LDS
+    th_v = eng.load_materials(T.tissue_blob() if variant == "tissues8" else T.standard_blob(variant))
+    ph = phantoms.random_field_phantom(40, 0.25, seed=61, nz=48)
+    if variant == "tissues8":
+        ph.mat = phantoms.tissue_from_density(ph.rho)
+        assert len(np.unique(ph.mat)) == 8
+    x, y = ph.centre_xy()
+    kind = {"spectrum": sources.spectrum_6mv()} if particle == PHOTON else {"energy": 12.0}
+    src = sources.point_field(particle, x, y, 60.0, 3.0, 2.0, **kind)
+    n = 20_000
+    pid = eng.load_phantom(ph, th_v)
+    auto = eng.launch_shape(pid, **kopt("wave"))["table_placement"]
+    assert auto == (TABLES_GLOBAL if variant == "tissues8" else TABLES_LDS)
+    out = {}
+    for place in (TABLES_LDS, TABLES_GLOBAL):
+        hist = torch.zeros(n * 4, dtype=torch.float64, device="cuda")
+        log(f"case global tables variant={variant} particle={particle} placement={place}")
+        r = eng.simulate(pid, src, n, 31, 4, n_vox=ph.n_vox, want_tallies=True, history_records=hist,
+                         table_placement=place, **kopt("wave"))
+        r["hist"] = np.frombuffer(hist.cpu().numpy().tobytes(), dtype=oracle.HISTORY_DTYPE)
+        out[place] = r
+    # the production build (no history records) as well
+    fast = {place: eng.simulate(pid, src, n, 31, 4, n_vox=ph.n_vox, want_tallies=True, table_placement=place,
+                                **kopt("wave")) for place in (TABLES_LDS, TABLES_GLOBAL)}
+    eng.unload_phantom(pid)
+    eng.unload_materials(th_v)
+    a, b = out[TABLES_LDS], out[TABLES_GLOBAL]
+    same = a["hist"]["hash"] == b["hist"]["hash"]
+    log(f"  LDS vs global tables: {same.mean():.5f} of histories identical")
+    assert same.all()
+    np.testing.assert_allclose(a["hist"]["edep"], b["hist"]["edep"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(a["hist"]["track_e"], b["hist"]["track_e"], rtol=1e-12, atol=1e-12)
+    for r0, r1 in ((a, b), (fast[TABLES_LDS], fast[TABLES_GLOBAL])):
+        S0, S1 = r0["S"].cpu().numpy(), r1["S"].cpu().numpy()
+        np.testing.assert_allclose(S1, S0, rtol=1e-5, atol=1e-9 * S0.max())
+        np.testing.assert_allclose(r1["dose"].cpu().numpy(), r0["dose"].cpu().numpy(), rtol=1e-5,
+                                   atol=1e-9 * r0["dose"].cpu().numpy().max())
+
+
+def test_launch_shape_and_table_placement_options(eng, th):
+    """mcd_launch_shape reports the default grid (the workgroups the device
+    holds at once for the wave-stack kernel), global tables free the LDS for
+    at least as many workgroups, and global tables are refused by the
+    schedules that do not support them."""
+    from paper_0910_0329_amd.mcdose import KERNEL_PLAIN, KERNEL_REGROUPED, TABLES_GLOBAL, TABLES_LDS
+    ph = phantoms.homogeneous(16, 16, 16, 1.0)
+    pid = eng.load_phantom(ph, th)
+    for bs in (256, 512):
+        lds = eng.launch_shape(pid, block_size=bs, table_placement=TABLES_LDS)
+        glob = eng.launch_shape(pid, block_size=bs, table_placement=TABLES_GLOBAL)
+        auto = eng.launch_shape(pid, block_size=bs)
+        log(f"  block {bs}: LDS tables {lds}, global tables {glob}, automatic {auto}")
+        assert lds["table_placement"] == TABLES_LDS and glob["table_placement"] == TABLES_GLOBAL
+        assert lds["resident_per_cu"] >= 1 and lds["grid_blocks"] == lds["cu_count"] * lds["resident_per_cu"]
+        assert glob["resident_per_cu"] >= lds["resident_per_cu"]
+        assert glob["grid_blocks"] == glob["cu_count"] * glob["resident_per_cu"]
+        # 64-wide waves, at most 32 per CU
+        assert glob["resident_per_cu"] * bs // 64 <= 32
+        # automatic: device memory only where the LDS copy costs workgroups
+        want = TABLES_GLOBAL if glob["resident_per_cu"] > lds["resident_per_cu"] else TABLES_LDS
+        assert auto == (glob if want == TABLES_GLOBAL else lds)
+    plain = eng.launch_shape(pid, kernel=KERNEL_PLAIN)
+    assert plain["resident_per_cu"] == 0 and plain["table_placement"] == TABLES_LDS
+    assert eng.launch_shape(pid, grid_blocks=77)["grid_blocks"] == 77
+    src = sources.pencil(PHOTON, 1.0, 8.0, 8.0)
+    for bad in ({"kernel": KERNEL_PLAIN}, {"kernel": KERNEL_REGROUPED, "regroup": 1},
+                {"kernel": KERNEL_REGROUPED, "regroup": 2}):
+        with pytest.raises(RuntimeError, match="table_placement"):
+            eng.simulate(pid, src, 1000, 1, n_vox=ph.n_vox, table_placement=TABLES_GLOBAL, **bad)
+    with pytest.raises(RuntimeError, match="table_placement"):
+        eng.launch_shape(pid, table_placement=3)
+    eng.unload_phantom(pid)
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("particle", [PHOTON, POSITRON])
 def test_lean_build_runs_the_same_histories(eng, blob, th, kernel, particle):

@@ -321,6 +321,38 @@ def test_majorant_bounds_every_voxel(blob, tabs):
     np.testing.assert_allclose(mu, best, rtol=1e-15)
 
 
+def test_tissue_mixtures_follow_their_compositions():
+    """The eight-tissue set's mixtures of water and bone have the per-gram
+    sums of the merged elemental compositions (water's and bone's elements at
+    their mass fractions), their mean excitation energy lies between the two
+    parts' (Bragg additivity in ln I), and the end points are the parts."""
+    water, bone = T.MATERIALS[T.MAT_WATER], T.MATERIALS[T.MAT_BONE]
+    for m in T.TISSUES8[4:]:
+        wb = {"adipose": 0.0, "muscle": 0.0, "cartilage": 0.1, "spongiosa": 0.4}[m.name]
+        comp = [(z, a, (1 - wb) * w) for z, a, w in T.COMPOSITIONS["water"]] + \
+               [(z, a, wb * w) for z, a, w in T.COMPOSITIONS["bone"]]
+        w, zoa, b, ee, p = _comp_sums(comp)
+        assert w == pytest.approx(1.0, abs=1e-6)
+        # the compositions reproduce water's atom to 1e-3 and bone's to 1e-4
+        for got, want in ((zoa, m.zoa), (b, m.b), (ee, m.ee), (p, m.p)):
+            assert got == pytest.approx(want, rel=1e-3), m.name
+        assert water.i_ev - 1e-9 <= m.i_ev <= bone.i_ev + 1e-9
+    for wb, ref in ((0.0, water), (1.0, bone)):
+        m = T.water_bone_mixture("x", ref.rho, wb)
+        for f in ("zoa", "i_ev", "b", "ee", "p"):
+            assert getattr(m, f) == pytest.approx(getattr(ref, f), rel=1e-12)
+    assert len(T.TISSUES8) == 8 and len({m.name for m in T.TISSUES8}) == 8
+
+
+def test_tissue_classes_by_density():
+    from paper_0910_0329_amd.inputs import phantoms
+    rho = np.array([0.0012, 0.0999, 0.1, 0.3, 0.5, 0.96, 0.97, 1.0, 1.02, 1.05, 1.08, 1.1, 1.14, 1.2, 1.3, 1.85])
+    want = [T.MAT_AIR, T.MAT_AIR, T.MAT_LUNG, T.MAT_LUNG, T.MAT_ADIPOSE, T.MAT_ADIPOSE, T.MAT_WATER, T.MAT_WATER,
+            T.MAT_MUSCLE, T.MAT_MUSCLE, T.MAT_CARTILAGE, T.MAT_CARTILAGE, T.MAT_SPONGIOSA, T.MAT_SPONGIOSA,
+            T.MAT_BONE, T.MAT_BONE]
+    np.testing.assert_array_equal(phantoms.tissue_from_density(rho), want)
+
+
 def test_random_field_phantom_statistics():
     from paper_0910_0329_amd.inputs import phantoms
     ph = phantoms.random_field_phantom(64, 0.5, seed=51)
