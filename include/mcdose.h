@@ -340,7 +340,7 @@ int mcd_launch_shape(mcd_ctx* ctx, int32_t phantom, const mcd_opts* opts, int32_
  * accumulators plus dose and sigma (nv doubles each), so a 256^3 phantom
  * costs 2.4 GB per request with FP64 sums and 1.3 GB with FP32 sums.  The
  * worker then runs epochs (RUNNING): one regrouped launch sequence over the
- * admitted requests of one phantom (phantoms taken in turn), in which every
+ * admitted requests of one phantom (chosen by mcd_serve_config.phantom_order), in which every
  * request advances by a slice of its histories.  Slices are handed out so
  * that the requests closest to completion finish first and the rest share
  * the epoch evenly.  A request's histories are the same whatever the slices:
@@ -351,6 +351,8 @@ int mcd_launch_shape(mcd_ctx* ctx, int32_t phantom, const mcd_opts* opts, int32_
  * mcd_wait collects it.  Not part of the paper, which runs one plan at a time. */
 enum { MCD_QUEUED = 0, MCD_ADMITTED = 1, MCD_RUNNING = 2, MCD_DONE = 3, MCD_FAILED = 4,
        MCD_CANCELED = 5 };
+/* mcd_serve_config.phantom_order */
+enum { MCD_PHANTOMS_SHORTEST = 0, MCD_PHANTOMS_IN_TURN = 1 };
 
 typedef struct {
     mcd_opts opts;              /* launch options of the epochs (block_size, grid_blocks,
@@ -361,7 +363,12 @@ typedef struct {
     uint64_t epoch_histories;   /* histories per epoch over all its requests, 0 = four cycles'
                                    worth (4 x lanes x chunk_per_lane) */
     int32_t max_active;         /* admitted requests at most, 0 = 4096 */
-    int32_t reserved;
+    int32_t phantom_order;      /* which phantom's requests the next epoch runs:
+                                   MCD_PHANTOMS_SHORTEST (0) = the phantom holding the request
+                                   with the fewest histories left, unless a phantom with
+                                   admitted requests has been passed over for 3 epochs in a
+                                   row (then the one passed over longest);
+                                   MCD_PHANTOMS_IN_TURN = phantoms in turn */
     uint64_t memory_limit;      /* bytes of request memory (tallies, dose, sigma) held at once,
                                    0 = only the context's HBM budget limits it */
 } mcd_serve_config;

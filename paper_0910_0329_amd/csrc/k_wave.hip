@@ -387,17 +387,21 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
             const int we = ne + nh + (int)min(se, 64u) + (can_claim && !claim_photon ? nf : 0);
             if (mode == ST_PHOTON ? (wp < low && we > wp) : (we < low && wp > we))
                 mode = ST_PHOTON + ST_ELECTRON - mode;
-            if (mode == ST_ELECTRON && np && se) {
-                swap_in(q, st, ST_PHOTON, ST_PHOTON, WS_ELECTRON, se);
-            } else if (mode == ST_PHOTON && ne + nh && sg) {
-                swap_in(q, st, ST_ELECTRON, ST_HARD, WS_PHOTON, sg);
+            unsigned stacked = sg + se;
+            const bool swap_e = mode == ST_ELECTRON && np && se;
+            const bool swap_p = mode == ST_PHOTON && ne + nh && sg;
+            if (swap_e || swap_p) {
+                if (swap_e) swap_in(q, st, ST_PHOTON, ST_PHOTON, WS_ELECTRON, se);
+                else swap_in(q, st, ST_ELECTRON, ST_HARD, WS_PHOTON, sg);
+                // the swapped lanes changed state and the stacks their counts
+                st = state(q);
+                nf = __popcll(__builtin_amdgcn_ballot_w64(st == ST_FETCH));
+                np = __popcll(__builtin_amdgcn_ballot_w64(st == ST_PHOTON));
+                nh = __popcll(__builtin_amdgcn_ballot_w64(st == ST_HARD));
+                ne = n - nf - np - nh;
+                stacked = cnt[WS_PHOTON] + cnt[WS_ELECTRON];
             }
-            st = state(q);
-            nf = __popcll(__builtin_amdgcn_ballot_w64(st == ST_FETCH));
-            np = __popcll(__builtin_amdgcn_ballot_w64(st == ST_PHOTON));
-            nh = __popcll(__builtin_amdgcn_ballot_w64(st == ST_HARD));
-            ne = n - nf - np - nh;
-            const bool fetchable = cnt[WS_PHOTON] + cnt[WS_ELECTRON] > 0 || can_claim;
+            const bool fetchable = stacked > 0 || can_claim;
             const int nfe = fetchable ? nf : 0;
             int act;
             if (nfe && (nfe * sc.fetch_div >= n || nfe == n)) act = ST_FETCH;

@@ -80,6 +80,10 @@ double ms_between(Clock::time_point a, Clock::time_point b)
 
 }  // namespace
 
+// An epoch on another phantom's requests passes a phantom over; after this
+// many in a row its requests run next (shortest-remaining order).
+constexpr int kMaxPassOver = 3;
+
 struct mcd_server {
     std::mutex mu;
     std::condition_variable cv_work;  // worker: something to do
@@ -93,6 +97,7 @@ struct mcd_server {
     std::deque<Request*> pending;                        // QUEUED, in arrival order
     std::vector<Request*> active;                        // ADMITTED or RUNNING
     int last_phantom = -1;
+    std::vector<int> passed;                             // epochs each phantom was passed over
     uint64_t req_bytes = 0;                              // memory held by requests
     bool mem_blocked = false;                            // the queue head waits for memory to be freed
     mcd_serve_stats stats{};
@@ -247,13 +252,39 @@ static void run_epoch(mcd_ctx* c, mcd_server* S)
         for (Request* r : S->active) (r->cancel ? dropped : keep).push_back(r);
         S->active.swap(keep);
         if (!S->active.empty()) {
-            // next phantom in turn that has admitted requests
             int pick = -1;
-            for (Request* r : S->active)
-                if (r->phantom > S->last_phantom && (pick < 0 || r->phantom < pick)) pick = r->phantom;
-            if (pick < 0)
+            if (S->cfg.phantom_order == MCD_PHANTOMS_IN_TURN) {
+                // next phantom in turn that has admitted requests
                 for (Request* r : S->active)
-                    if (pick < 0 || r->phantom < pick) pick = r->phantom;
+                    if (r->phantom > S->last_phantom && (pick < 0 || r->phantom < pick)) pick = r->phantom;
+                if (pick < 0)
+                    for (Request* r : S->active)
+                        if (pick < 0 || r->phantom < pick) pick = r->phantom;
+            } else {
+                // the phantom passed over longest once that reaches kMaxPassOver
+                // epochs, else the one holding the request with the fewest
+                // histories left (ties: the lower handle)
+                if (S->passed.size() < c->phantoms.size()) S->passed.resize(c->phantoms.size(), 0);
+                int starved = -1;
+                uint64_t fewest = 0;
+                for (Request* r : S->active) {
+                    const int p = r->phantom;
+                    if (S->passed[p] >= kMaxPassOver &&
+                        (starved < 0 || S->passed[p] > S->passed[starved] ||
+                         (S->passed[p] == S->passed[starved] && p < starved)))
+                        starved = p;
+                    const uint64_t left = r->n - r->done;
+                    if (pick < 0 || left < fewest || (left == fewest && p < pick)) {
+                        pick = p;
+                        fewest = left;
+                    }
+                }
+                if (starved >= 0) pick = starved;
+                // every other phantom with admitted requests waits one more epoch
+                std::vector<char> waits(S->passed.size(), 0);
+                for (Request* r : S->active) waits[r->phantom] = r->phantom != pick;
+                for (size_t p = 0; p < waits.size(); ++p) S->passed[p] = waits[p] ? S->passed[p] + 1 : 0;
+            }
             S->last_phantom = pick;
             for (Request* r : S->active)
                 if (r->phantom == pick && (int)batch.size() < kMaxBatch) batch.push_back(r);
@@ -278,10 +309,10 @@ static void run_epoch(mcd_ctx* c, mcd_server* S)
         if (c->launch_shape(&S->cfg.opts, c->tables[ph.tables].n_mat, &blocks, &threads) != MCD_OK)
             blocks = threads = 1;
         const int cpl = S->cfg.opts.chunk_per_lane ? S->cfg.opts.chunk_per_lane : kDefaultChunkPerLane;
-        // four cycles' worth: each epoch ends with a drain in which few lanes
-        // are busy, and on a loaded server longer epochs pay for fewer of them
-        // (the 20 req/s mixed stream measured +3.5% and lower p50 and p99
-        // against two cycles; eight cycles add 1% more)
+        // four cycles' worth: each epoch ends with a tail in which few waves
+        // are busy, so short epochs pay more tails, and long ones hold small
+        // requests back (on the 20 req/s mixed stream half this size raised
+        // p99 by 16%, twice this size p50 by 24%)
         budget = 4 * (uint64_t)blocks * threads * (uint64_t)cpl;
     }
     std::sort(batch.begin(), batch.end(),
@@ -451,6 +482,8 @@ static int check_config(mcd_ctx* c, const mcd_serve_config* cfg)
         return c->fail(MCD_E_INVAL, "serve config: max_active in [0, 4096]");
     if (cfg->epoch_histories >= ((uint64_t)1 << 40))
         return c->fail(MCD_E_INVAL, "serve config: epoch_histories < 2^40");
+    if (cfg->phantom_order != MCD_PHANTOMS_SHORTEST && cfg->phantom_order != MCD_PHANTOMS_IN_TURN)
+        return c->fail(MCD_E_INVAL, "serve config: phantom_order must be MCD_PHANTOMS_SHORTEST or _IN_TURN");
     int b = 0, t = 0;
     return c->launch_shape(&o, 1, &b, &t);
 }

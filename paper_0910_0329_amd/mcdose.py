@@ -79,12 +79,13 @@ class BatchItem(C.Structure):
 
 
 QUEUED, ADMITTED, RUNNING, DONE, FAILED, CANCELED = range(6)
+PHANTOMS_SHORTEST, PHANTOMS_IN_TURN = 0, 1               # mcd_serve_config.phantom_order
 STATE_NAMES = ("queued", "admitted", "running", "done", "failed", "canceled")
 
 
 class ServeConfig(C.Structure):
     _fields_ = [("opts", Opts), ("epoch_histories", C.c_uint64), ("max_active", C.c_int32),
-                ("reserved", C.c_int32), ("memory_limit", C.c_uint64)]
+                ("phantom_order", C.c_int32), ("memory_limit", C.c_uint64)]
 
 
 class ServeStats(C.Structure):
@@ -388,11 +389,12 @@ class Engine:
     # ------------------------------------------------------------ serving
 
     def serve_configure(self, epoch_histories: int = 0, max_active: int = 0, memory_limit: int = 0,
-                        **opts):
+                        phantom_order: int = 0, **opts):
         cfg = ServeConfig()
         cfg.opts = make_opts(**opts)
         cfg.epoch_histories = epoch_histories
         cfg.max_active = max_active
+        cfg.phantom_order = phantom_order
         cfg.memory_limit = memory_limit
         self._check(lib().mcd_serve_configure(self._h, C.byref(cfg)), "mcd_serve_configure")
 

@@ -80,11 +80,15 @@ def same(a, b, ph):
     assert a["sigma_bar"] == pytest.approx(b["sigma_bar"], rel=1e-6)
 
 
-def test_served_equals_standalone(eng, pool):
-    """Small epochs (many slices per request), requests of two phantoms."""
+@pytest.mark.parametrize("order", ("shortest", "in_turn"))
+def test_served_equals_standalone(eng, pool, order):
+    """Small epochs (many slices per request), requests of two phantoms taken
+    in either phantom order."""
+    from paper_0910_0329_amd.mcdose import PHANTOMS_IN_TURN, PHANTOMS_SHORTEST
     items = mix(pool)
-    log("case serve mix, epoch_histories=6000")
-    eng.serve_configure(epoch_histories=6000, regroup=2)
+    log(f"case serve mix, epoch_histories=6000, phantom order {order}")
+    eng.serve_configure(epoch_histories=6000, regroup=2,
+                        phantom_order=PHANTOMS_SHORTEST if order == "shortest" else PHANTOMS_IN_TURN)
     tickets = [eng.submit(pool[sl][0], src, n, seed, key) for sl, src, n, seed, key in items]
     outs = [eng.wait(t, n_vox=pool[it[0]][1].n_vox) for t, it in zip(tickets, items)]
     st = eng.serve_stats()
@@ -241,6 +245,14 @@ def test_memory_limit_admission(eng, pool, th):
         eng.wait(tb, n_vox=big_ph.n_vox)
     assert ei.value.status == E_NOMEM
     eng.unload_phantom(big)
+
+
+def test_phantom_order_is_validated(eng):
+    from paper_0910_0329_amd.mcdose import E_INVAL, McdError
+    with pytest.raises(McdError) as ei:
+        eng.serve_configure(phantom_order=2)
+    assert ei.value.status == E_INVAL
+    eng.serve_configure()
 
 
 def test_unload_busy_and_bad_tickets(eng, pool):
