@@ -49,8 +49,8 @@ sys.path.insert(0, ROOT)
 # of each workload divided by 2e5 (profiles/transport_lockstep_valu.md).  Each
 # VALU instruction of that path is one lane-op of the history's own work.
 PATH_LANE_OPS = {
-    "g6mv_wbw_61x61x60": 3464737789 / 200_000,     # 17323.7
-    "e20_wlw_32x32x30": 13295921535 / 200_000,     # 66479.6
+    "g6mv_wbw_61x61x60": 3442984358 / 200_000,     # 17214.9
+    "e20_wlw_32x32x30": 13406747769 / 200_000,     # 67033.7
 }
 # Plain VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # = 3.93e13 lane-ops/s (one non-packed FP32/INT32 op per lane per cycle).
@@ -60,8 +60,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # its reading for a 1 GiB device copy (profiles/transport_g6mv_hbm_traffic.md,
 # profiles/transport_e20_wlw_hbm_traffic.md).
 TRAFFIC_BYTES_PER_HIST = {
-    "g6mv_wbw_61x61x60": (17239292.44 * 2.0 + 46302278.0 * 1.0) * 1024 / 164442762,    # 503.0
-    "e20_wlw_32x32x30": (765361.75 * 2.0 + 16117193.66 * 1.0) * 1024 / 10_000_000,     # 1807.1
+    "g6mv_wbw_61x61x60": (17246111.44 * 2.0 + 46333846.78 * 1.0) * 1024 / 164442762,   # 503.3
+    "e20_wlw_32x32x30": (754803.69 * 2.0 + 16060823.47 * 1.0) * 1024 / 10_000_000,     # 1799.2
 }
 METRIC = "histories/s (6 MV photon, 20 MeV e-) at 1% sigma; p50/p99 dose-request latency"
 # The paper's Table 1 (Tesla C1060, FP32; DPM physics and a measured 6 MV

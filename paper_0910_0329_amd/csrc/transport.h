@@ -36,6 +36,14 @@ enum { EV_VIRTUAL = 1, EV_COMPTON, EV_PHOTO, EV_PAIR, EV_PAIR_VOID, EV_G_ESCAPE,
        EV_SEG = 10, EV_MOLLER = 20, EV_BREMS, EV_MOLLER_VOID, EV_E_ESCAPE, EV_BHABHA, EV_BHABHA_VOID };
 
 DEV float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// Hardware square root and base-2 exponential (v_sqrt_f32, v_exp_f32, about
+// 1 ulp) in place of the correctly rounded library forms, which add up to a
+// dozen instructions each for denormal scaling and rounding fix-up.  The
+// transport's square roots take normal numbers or zero, and its exponentials
+// give normal numbers, except the Rayleigh screening factor (1 + 2b)^-3,
+// which is subtracted from 1 and vanishes there either way.
+DEV float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+DEV float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // Linear interpolation between two table nodes (fr in [0, 1)); every table
 // lookup of the transport goes through it.
@@ -308,7 +316,7 @@ struct Transport {
         }
         const float r0 = rj, r1 = rn;
         const float fr = fminf(fdiv(r - r0, r1 - r0), 1.0f);
-        return exp2f(G().t.l2_emin + ((float)j + fr) * G().t.dl2);
+        return fexp2(G().t.l2_emin + ((float)j + fr) * G().t.dl2);
     }
 
     // --------------------------------------------------------- geometry
@@ -363,7 +371,7 @@ struct Transport {
     {
         const float cost = 2.f * uni(q) - 1.f;
         const float ph = uni(q);
-        const float sint = sqrtf(fmaxf(0.f, 1.f - cost * cost));
+        const float sint = fsqrt(fmaxf(0.f, 1.f - cost * cost));
         const float cp = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
         const float dx = sint * cp, dy = sint * sph;
         emit_photon(q, kMC2, x, y, z, dx, dy, cost, vox);
@@ -397,7 +405,7 @@ struct Transport {
     DEV static void beta_a(float t, float& b, float& a)
     {
         const float g = 1.f + fdiv(t, kMC2);
-        b = fdiv(sqrtf(t * (t + 2.f * kMC2)), t + kMC2);
+        b = fdiv(fsqrt(t * (t + 2.f * kMC2)), t + kMC2);
         a = __builtin_amdgcn_rcpf(b * g * g * (1.f + b));
     }
 
@@ -427,7 +435,7 @@ struct Transport {
         const float xmax = fdiv(2.f, a + 2.f);
         const float m = c >= 0.f ? 1.f + c * (a + 2.f) : 1.f + c * a;
         for (;;) {
-            const float x = xmax * sqrtf(uni(q));
+            const float x = xmax * fsqrt(uni(q));
             const float nu = fdiv(a * x, 1.f - x);
             const float acc = fdiv((1.f - x) * (2.f - nu) * (1.f + c * (a + nu)), 2.f * m);
             if (uni(q) <= acc) return fmaxf(1.f - nu, -1.f);
@@ -443,11 +451,11 @@ struct Transport {
     // a few ulp of 1 in c.
     DEV float rayleigh_cos(Part& q, float b)
     {
-        const float w = 1.f - exp2f(-3.f * __log2f(1.f + 2.f * b));
+        const float w = 1.f - fexp2(-3.f * __log2f(1.f + 2.f * b));
         const float ib = __builtin_amdgcn_rcpf(b);
         for (;;) {
             const float u = uni(q);
-            const float s = fminf((exp2f(__log2f(1.f - u * w) * (-1.f / 3.f)) - 1.f) * ib, 2.f);
+            const float s = fminf((fexp2(__log2f(1.f - u * w) * (-1.f / 3.f)) - 1.f) * ib, 2.f);
             const float c = 1.f - s;
             if (uni(q) <= 0.5f * (1.f + c * c)) return c;
         }
@@ -457,8 +465,8 @@ struct Transport {
     // Rotates (u, v, w) by polar cosine cost and azimuth (cos, sin) = (cp, sph).
     DEV static void rotate(float& u, float& v, float& w, float cost, float cp, float sph)
     {
-        const float sint = sqrtf(fmaxf(0.f, 1.f - cost * cost));
-        const float s = sqrtf(u * u + v * v);
+        const float sint = fsqrt(fmaxf(0.f, 1.f - cost * cost));
+        const float s = fsqrt(u * u + v * v);
         float nu, nv, nw;
         if (s < 1e-7f) {
             nu = sint * cp;
@@ -669,8 +677,8 @@ struct Transport {
             ensure(q, 4);                      // three for the try, one for the azimuth
             const float ua = uni_ready(q), ub = uni_ready(q), uc = uni_ready(q);
             count(MCD_C_COMPTON_TRIES);
-            if (ua * (a1 + a2) < a1) tau = exp2f(ub * l2tmin);
-            else tau = sqrtf(tmin * tmin + ub * (1.f - tmin * tmin));
+            if (ua * (a1 + a2) < a1) tau = fexp2(ub * l2tmin);
+            else tau = fsqrt(tmin * tmin + ub * (1.f - tmin * tmin));
             cost = 1.f - fdiv(1.f - tau, k * tau);
             const float sin2 = 1.f - cost * cost;
             if (uc <= 1.f - fdiv(tau * sin2, 1.f + tau * tau)) break;
@@ -883,8 +891,8 @@ struct Transport {
         const float cp = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
         const float tn = T - eps * T;          // the positron keeps exactly T - W
         const float wd = T - tn;
-        const float cs = sqrtf(fdiv(wd * (T + 2.f * kMC2), T * (wd + 2.f * kMC2)));
-        const float cpr = sqrtf(fdiv(tn * (T + 2.f * kMC2), T * (tn + 2.f * kMC2)));
+        const float cs = fsqrt(fdiv(wd * (T + 2.f * kMC2), T * (wd + 2.f * kMC2)));
+        const float cpr = fsqrt(fdiv(tn * (T + 2.f * kMC2), T * (tn + 2.f * kMC2)));
         float du = q.u, dv = q.v, dw = q.w;
         rotate(du, dv, dw, fminf(cs, 1.f), -cp, -sph);
         emit_charged(q, ELECTRON, wd, q.x, q.y, q.z, du, dv, dw, vx);
@@ -938,8 +946,8 @@ struct Transport {
                 const float cp = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
                 const float tn = T - eps * T;      // primary keeps exactly T - W
                 const float wd = T - tn;
-                const float cs = sqrtf(fdiv(wd * (T + 2.f * kMC2), T * (wd + 2.f * kMC2)));
-                const float cpr = sqrtf(fdiv(tn * (T + 2.f * kMC2), T * (tn + 2.f * kMC2)));
+                const float cs = fsqrt(fdiv(wd * (T + 2.f * kMC2), T * (wd + 2.f * kMC2)));
+                const float cpr = fsqrt(fdiv(tn * (T + 2.f * kMC2), T * (tn + 2.f * kMC2)));
                 float du = q.u, dv = q.v, dw = q.w;
                 rotate(du, dv, dw, fminf(cs, 1.f), -cp, -sph);
                 emit_charged(q, ELECTRON, wd, q.x, q.y, q.z, du, dv, dw, vx);
@@ -949,7 +957,7 @@ struct Transport {
         } else {
             ev(EV_BREMS);
             count(MCD_C_BREMS);
-            const float w = fminf(g.t.w_cr * exp2f(uni(q) * __log2f(fdiv(T, g.t.w_cr))), T);
+            const float w = fminf(g.t.w_cr * fexp2(uni(q) * __log2f(fdiv(T, g.t.w_cr))), T);
             // the photon goes along the electron, or (angular tables) at a
             // forward angle to it; the azimuth is drawn either way
             const float ph = uni(q);
