@@ -228,13 +228,16 @@ struct Transport {
         if (4u * q.g - q.d < n) refill(q);
     }
 
+    // Word d mod 8 of the ring, chosen by a select tree on the bits of d
+    // (seven selects, no branch: the lanes of a wave draw different words).
     DEV float uni_ready(Part& q)
     {
-        const uint32_t k = q.d & 3u;
-        uint32_t x;
-        if ((q.d >> 2) & 1u) x = k == 0 ? q.r4 : (k == 1 ? q.r5 : (k == 2 ? q.r6 : q.r7));
-        else x = k == 0 ? q.r0 : (k == 1 ? q.r1 : (k == 2 ? q.r2 : q.r3));
-        ++q.d;
+        const uint32_t d = q.d;
+        const bool b0 = (d & 1u) != 0, b1 = (d & 2u) != 0, b2 = (d & 4u) != 0;
+        const uint32_t w01 = b0 ? q.r1 : q.r0, w23 = b0 ? q.r3 : q.r2;
+        const uint32_t w45 = b0 ? q.r5 : q.r4, w67 = b0 ? q.r7 : q.r6;
+        const uint32_t x = b2 ? (b1 ? w67 : w45) : (b1 ? w23 : w01);
+        q.d = d + 1u;
         return ((float)(x >> 9) + 0.5f) * 0x1p-23f;
     }
 
