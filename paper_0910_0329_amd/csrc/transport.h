@@ -205,11 +205,13 @@ struct Transport {
     // at the same time, so the rounds run for many lanes at once instead of
     // for a few lanes at almost every step.  After it every lane holds at
     // least two words, which those draws take with uni_ready; later draws
-    // check the ring (uni, or ensure once per rejection-loop try).
-    DEV void prefetch(Part& q)
+    // check the ring (uni, or ensure once per rejection-loop try).  The
+    // rejection samplers call it with n = 4 before their loops, so that their
+    // first try (which most accept) draws without a refill of a few lanes.
+    DEV void prefetch(Part& q, uint32_t n = 2u)
     {
         const bool slot = (q.d >> 2) + 1u >= q.g;
-        const bool need = 4u * q.g - q.d < 2u;
+        const bool need = 4u * q.g - q.d < n;
         if (__builtin_amdgcn_ballot_w64(need) != 0 && slot) refill(q);
     }
 
@@ -676,6 +678,7 @@ struct Transport {
         const float a2 = 2.f * k * (1.f + k) * tmin * tmin;
         const float l2tmin = __log2f(tmin);
         float tau, cost;
+        prefetch(q, 4u);
         for (;;) {
             ensure(q, 4);                      // three for the try, one for the azimuth
             const float ua = uni_ready(q), ub = uni_ready(q), uc = uni_ready(q);
@@ -798,9 +801,13 @@ struct Transport {
         } else if (lim == LIM_H) {
             q.pend = 1;                   // sampled by hard_event when the wave runs them
         } else if (lim == LIM_K) {
-            if (q.before) {
+            // one uniform for every lane: the hinge's polar draw, or after the
+            // hinge the next step's hinge fraction; only the deflection is
+            // left to the lanes at a hinge
+            const float u = uni_ready(q);          // prefetch left >= 2 words
+            const bool hinge = q.before != 0;
+            if (hinge) {
                 count(MCD_C_HINGES);
-                const float u = uni_ready(q);      // prefetch left >= 2 words
                 float mu;
                 if (REF && g.t.hinge2) {
                     // second-moment law at the energy the hinge is reached
@@ -822,25 +829,20 @@ struct Transport {
                 const float ph = uni_ready(q);
                 rotate(q.u, q.v, q.w, 1.f - 2.f * mu, __builtin_amdgcn_cosf(ph),
                        __builtin_amdgcn_sinf(ph));
-                q.kap = (1.f - q.xi) * g.t.kappa_step;
-                q.before = 0;
-            } else {
-                q.xi = uni_ready(q);
-                q.kap = q.xi * g.t.kappa_step;
-                q.before = 1;
             }
+            q.kap = (hinge ? 1.f - q.xi : u) * g.t.kappa_step;
+            q.xi = hinge ? q.xi : u;
+            q.before = hinge ? 0 : 1;
         } else if (lim == LIM_B) {
-            bool out;
-            if (axis == 0) {
-                q.ix += q.u > 0.f ? 1 : -1;
-                out = q.ix < 0 || q.ix >= g.nx;
-            } else if (axis == 1) {
-                q.iy += q.v > 0.f ? 1 : -1;
-                out = q.iy < 0 || q.iy >= g.ny;
-            } else {
-                q.iz += q.w > 0.f ? 1 : -1;
-                out = q.iz < 0 || q.iz >= g.nz;
-            }
+            // one voxel along the crossed axis, with selects (lanes cross
+            // different faces)
+            const float da = axis == 0 ? q.u : (axis == 1 ? q.v : q.w);
+            const int st = da > 0.f ? 1 : -1;
+            q.ix += axis == 0 ? st : 0;
+            q.iy += axis == 1 ? st : 0;
+            q.iz += axis == 2 ? st : 0;
+            const bool out = (unsigned)q.ix >= (unsigned)g.nx || (unsigned)q.iy >= (unsigned)g.ny ||
+                             (unsigned)q.iz >= (unsigned)g.nz;
             if (out) {
                 ev(EV_E_ESCAPE);
                 e_esc += (double)q.e + (q.type == POSITRON ? 2.0 * (double)kMC2 : 0.0);
@@ -907,6 +909,7 @@ struct Transport {
     {
         const KGeom& g = G();
         q.pend = 0;
+        prefetch(q, 4u);                       // the choice, a Moller try and its azimuth
         const int vx = lin(q.ix, q.iy, q.iz);
         const int m = (int)g.vox[vx].y;
         float T = q.e;
