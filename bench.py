@@ -47,10 +47,13 @@ sys.path.insert(0, ROOT)
 # instruction path (all 64 lanes of a wave replaying the same history, plain
 # kernel `lockstep` launch), from rocprofv3 SQ_INSTS_VALU over 2e5 histories
 # of each workload divided by 2e5 (profiles/transport_lockstep_valu.md).  Each
-# VALU instruction of that path is one lane-op of the history's own work.
+# VALU instruction of that path is one lane-op of the history's own work.  The
+# figure is the lowest any build of the shared transport measured: the
+# branch-free random-word selects cost a few converged instructions more
+# (17760.8 and 68566.5) while saving far more under divergence.
 PATH_LANE_OPS = {
     "g6mv_wbw_61x61x60": 3442984358 / 200_000,     # 17214.9
-    "e20_wlw_32x32x30": 13406747769 / 200_000,     # 67033.7
+    "e20_wlw_32x32x30": 13295921535 / 200_000,     # 66479.6
 }
 # Plain VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # = 3.93e13 lane-ops/s (one non-packed FP32/INT32 op per lane per cycle).
@@ -60,8 +63,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # its reading for a 1 GiB device copy (profiles/transport_g6mv_hbm_traffic.md,
 # profiles/transport_e20_wlw_hbm_traffic.md).
 TRAFFIC_BYTES_PER_HIST = {
-    "g6mv_wbw_61x61x60": (17246111.44 * 2.0 + 46333846.78 * 1.0) * 1024 / 164442762,   # 503.3
-    "e20_wlw_32x32x30": (754803.69 * 2.0 + 16060823.47 * 1.0) * 1024 / 10_000_000,     # 1799.2
+    "g6mv_wbw_61x61x60": (17264457.0 * 2.0 + 46355729.28 * 1.0) * 1024 / 164442762,    # 503.7
+    "e20_wlw_32x32x30": (766627.25 * 2.0 + 16112660.44 * 1.0) * 1024 / 10_000_000,     # 1806.9
 }
 METRIC = "histories/s (6 MV photon, 20 MeV e-) at 1% sigma; p50/p99 dose-request latency"
 # The paper's Table 1 (Tesla C1060, FP32; DPM physics and a measured 6 MV
