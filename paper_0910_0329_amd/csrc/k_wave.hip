@@ -322,8 +322,11 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
         const unsigned ta = min(nfl, ca), tb = can_claim ? 0u : min(nfl - ta, cb);
         cnt[ka] = ca - ta;
         cnt[kb] = cb - tb;
-        if (rank < ta) take(ka, ca - 1 - rank, q);
-        else if (rank < ta + tb) take(kb, cb - 1 - (rank - ta), q);
+        // one take for both stacks (lanes of a fetch may take from either)
+        if (rank < ta + tb) {
+            const bool a = rank < ta;
+            take(a ? ka : kb, a ? ca - 1 - rank : cb - 1 - (rank - ta), q);
+        }
         // every record taken above is read before a new history below can
         // push onto the slots just freed (a positron primary below its
         // cutoff annihilates at once)
