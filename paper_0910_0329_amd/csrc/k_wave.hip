@@ -309,16 +309,18 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
 
     // Fetch step of the lanes that need a particle: first the stack of the
     // wave's mode, then new histories while they may start, else the other
-    // stack.  Returns false only for a lane whose claim found the histories
-    // exhausted (claims held back by full stacks are not exhaustion).
-    DEV bool fetch_wave(Part& q, bool prefer_photons, bool can_claim)
+    // stack.  sg and se are the stacks' current counts (the caller's copies
+    // of the LDS words).  Returns false only for a lane whose claim found the
+    // histories exhausted (claims held back by full stacks are not
+    // exhaustion).
+    DEV bool fetch_wave(Part& q, bool prefer_photons, bool can_claim, unsigned sg, unsigned se)
     {
         const uint64_t m = __builtin_amdgcn_ballot_w64(true);
         const unsigned rank =
             __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         const unsigned nfl = (unsigned)__popcll(m);
         const int ka = prefer_photons ? WS_PHOTON : WS_ELECTRON, kb = 1 - ka;
-        const unsigned ca = cnt[ka], cb = cnt[kb];
+        const unsigned ca = prefer_photons ? sg : se, cb = prefer_photons ? se : sg;
         const unsigned ta = min(nfl, ca), tb = can_claim ? 0u : min(nfl - ta, cb);
         cnt[ka] = ca - ta;
         cnt[kb] = cb - tb;
@@ -390,21 +392,31 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
             const int we = ne + nh + (int)min(se, 64u) + (can_claim && !claim_photon ? nf : 0);
             if (mode == ST_PHOTON ? (wp < low && we > wp) : (we < low && wp > we))
                 mode = ST_PHOTON + ST_ELECTRON - mode;
-            unsigned stacked = sg + se;
+            // a swap parks k particles on their own kind's stack and takes k
+            // from the other: the counts move by k and their sum stays
+            unsigned sgn = sg, sen = se;
             const bool swap_e = mode == ST_ELECTRON && np && se;
             const bool swap_p = mode == ST_PHOTON && ne + nh && sg;
             if (swap_e || swap_p) {
-                if (swap_e) swap_in(q, st, ST_PHOTON, ST_PHOTON, WS_ELECTRON, se);
-                else swap_in(q, st, ST_ELECTRON, ST_HARD, WS_PHOTON, sg);
-                // the swapped lanes changed state and the stacks their counts
+                if (swap_e) {
+                    swap_in(q, st, ST_PHOTON, ST_PHOTON, WS_ELECTRON, se);
+                    const unsigned k = min((unsigned)np, se);
+                    sgn = sg + k;
+                    sen = se - k;
+                } else {
+                    swap_in(q, st, ST_ELECTRON, ST_HARD, WS_PHOTON, sg);
+                    const unsigned k = min((unsigned)(ne + nh), sg);
+                    sen = se + k;
+                    sgn = sg - k;
+                }
+                // the swapped lanes changed state
                 st = state(q);
                 nf = __popcll(__builtin_amdgcn_ballot_w64(st == ST_FETCH));
                 np = __popcll(__builtin_amdgcn_ballot_w64(st == ST_PHOTON));
                 nh = __popcll(__builtin_amdgcn_ballot_w64(st == ST_HARD));
                 ne = n - nf - np - nh;
-                stacked = cnt[WS_PHOTON] + cnt[WS_ELECTRON];
             }
-            const bool fetchable = stacked > 0 || can_claim;
+            const bool fetchable = sg + se > 0 || can_claim;
             const int nfe = fetchable ? nf : 0;
             int act;
             if (nfe && (nfe * sc.fetch_div >= n || nfe == n)) act = ST_FETCH;
@@ -424,7 +436,7 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
             bool exhausted = false;
             if (st == act) {
                 if (act == ST_FETCH) {
-                    exhausted = !fetch_wave(q, mode == ST_PHOTON, can_claim);
+                    exhausted = !fetch_wave(q, mode == ST_PHOTON, can_claim, sgn, sen);
                 } else if (act == ST_PHOTON) {
                     this->photon_step(q);
                 } else if (act == ST_ELECTRON) {
