@@ -480,6 +480,25 @@ int mcd_check_tables(mcd_ctx* ctx, int32_t phantom, int32_t material, int32_t qu
 int mcd_measure_atomics(mcd_ctx* ctx, double* target, uint64_t n_target, const uint32_t* idx, uint64_t n,
                         int32_t reps, double* ms, void* hip_stream);
 
+/* Issue rate of one kind of VALU instruction: every lane of eight waves per
+ * SIMD runs `iters` x 128 operations in eight independent chains (no loads
+ * or stores in the loop), and *cycles_per_op (host) receives the SIMD cycles
+ * per wave-wide operation at the device's peak engine clock.  Kinds:
+ *   MCD_VALU_FMA_F32  one v_fma_f32
+ *   MCD_VALU_ADD_F32  one v_add_f32
+ *   MCD_VALU_MUL_F32  one v_mul_f32
+ *   MCD_VALU_XAD_U32  one 32-bit xor-add (v_xad_u32)
+ *   MCD_VALU_MAD_U64  a 32 x 32 -> 64-bit multiply (v_mad_u64_u32) and an xor,
+ *                     the Philox round's product
+ *   MCD_VALU_FMAMK_F32 one FMA with literal constants (v_fmamk_f32).
+ * A wave64 instruction on a 16-lane SIMD takes 4 cycles; fewer means the
+ * hardware issues it on wider datapaths.  sink: one device float the kernel
+ * never writes in practice.  For the transport's ALU roofline. */
+enum { MCD_VALU_FMA_F32 = 0, MCD_VALU_ADD_F32 = 1, MCD_VALU_MUL_F32 = 2, MCD_VALU_XAD_U32 = 3,
+       MCD_VALU_MAD_U64 = 4, MCD_VALU_FMAMK_F32 = 5 };
+int mcd_measure_valu(mcd_ctx* ctx, int32_t kind, int32_t iters, float* sink, double* cycles_per_op,
+                     void* hip_stream);
+
 /* Status and error text.  mcd_last_error reports the last failure of a call
  * made on this context by the calling thread. */
 const char* mcd_status_string(int status);

@@ -91,6 +91,53 @@ __global__ __launch_bounds__(256) void k_atomic_stream(double* target, uint64_t 
         }
 }
 
+// Issue-rate probe: eight independent chains per lane of one instruction
+// kind, 16 x 8 operations per iteration; the result is stored only in a case
+// no input reaches, so nothing is optimised away.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_valu_rate(float x, uint32_t y, int iters, float* sink)
+{
+    float f[8];
+    uint32_t u[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        f[c] = (float)threadIdx.x * 1e-3f + (float)c;
+        u[c] = threadIdx.x * 7u + (uint32_t)c;
+    }
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                if (KIND == MCD_VALU_FMA_F32) {
+                    f[c] = __builtin_fmaf(f[c], x, 0.001f);
+                } else if (KIND == MCD_VALU_FMAMK_F32) {
+                    f[c] = __builtin_fmaf(f[c], 0.999f, 0.001f);
+                } else if (KIND == MCD_VALU_ADD_F32) {
+                    f[c] = f[c] + x;
+                } else if (KIND == MCD_VALU_MUL_F32) {
+                    f[c] = f[c] * x;
+                } else if (KIND == MCD_VALU_XAD_U32) {
+                    u[c] = (u[c] ^ (y + (uint32_t)r)) + (uint32_t)c;
+                } else {
+                    const uint64_t pr = (uint64_t)y * u[c];
+                    u[c] = (uint32_t)(pr >> 32) ^ (uint32_t)pr;
+                }
+            }
+        }
+    }
+    float fs = 0.f;
+    uint32_t us = 0u;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        fs += f[c];
+        us ^= u[c];
+    }
+    const bool fp = KIND == MCD_VALU_FMA_F32 || KIND == MCD_VALU_ADD_F32 || KIND == MCD_VALU_MUL_F32 ||
+                    KIND == MCD_VALU_FMAMK_F32;
+    if (fp ? fs == -12345.f : us == y + 0x9E3779B9u) sink[0] = fs + (float)us;
+}
+
 hipError_t init_check_kernels(int max_lds)
 {
     return hipFuncSetAttribute((const void*)k_check_tables, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
@@ -173,5 +220,39 @@ int mcd_measure_atomics(mcd_ctx* c, double* target, uint64_t n_target, const uin
     if (e == hipSuccess) e = hipEventElapsedTime(&t, c->ev[0], c->ev[1]);
     if (e != hipSuccess) return c->hip_fail(e, "measure_atomics");
     *ms = t;
+    return MCD_OK;
+}
+
+int mcd_measure_valu(mcd_ctx* c, int32_t kind, int32_t iters, float* sink, double* cycles_per_op,
+                     void* hip_stream)
+{
+    if (!c) return MCD_E_INVAL;
+    if (!sink || !cycles_per_op || kind < MCD_VALU_FMA_F32 || kind > MCD_VALU_FMAMK_F32 || iters < 1 ||
+        iters > 100000)
+        return c->fail(MCD_E_INVAL, "measure_valu: need a device sink, a known kind, 1 <= iters <= 1e5");
+    mcd::DeviceGuard dg(c->device);
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    // eight waves per SIMD: the issue rate, not the latency, sets the time
+    const int threads = 256, blocks = c->cu_count * 8;
+    void (*k)(float, uint32_t, int, float*) =
+        kind == MCD_VALU_FMA_F32 ? k_valu_rate<MCD_VALU_FMA_F32>
+        : kind == MCD_VALU_ADD_F32 ? k_valu_rate<MCD_VALU_ADD_F32>
+        : kind == MCD_VALU_MUL_F32 ? k_valu_rate<MCD_VALU_MUL_F32>
+        : kind == MCD_VALU_XAD_U32 ? k_valu_rate<MCD_VALU_XAD_U32>
+        : kind == MCD_VALU_MAD_U64 ? k_valu_rate<MCD_VALU_MAD_U64>
+                                   : k_valu_rate<MCD_VALU_FMAMK_F32>;
+    hipError_t e = hipEventRecord(c->ev[0], s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), 0, s, 1.0001f, 0xD2511F53u, iters, sink);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->ev[1], s);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ev[1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+    if (e != hipSuccess) return c->hip_fail(e, "measure_valu");
+    const double wave_ops = (double)blocks * (threads / 64) * (double)iters * 16.0 * 8.0;
+    const double simd_cycles = (double)ms * 1e-3 * (double)c->cu_count * 4.0 * (double)c->clock_khz * 1e3;
+    *cycles_per_op = simd_cycles / wave_ops;
     return MCD_OK;
 }

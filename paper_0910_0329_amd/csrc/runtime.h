@@ -207,6 +207,7 @@ private:
 struct mcd_ctx {
     int device = 0;
     int cu_count = 0;
+    int clock_khz = 0;        // peak engine clock
     int max_lds = 0;     // dynamic LDS bytes a workgroup may use
     hipStream_t stream = nullptr;
     uint64_t budget = 0, used = 0;

@@ -121,6 +121,7 @@ int mcd_create(int device, uint64_t hbm_budget_bytes, mcd_ctx** out)
         return MCD_E_DEVICE;
     }
     c->cu_count = prop.multiProcessorCount;
+    c->clock_khz = prop.clockRate;
     c->max_lds = (int)prop.sharedMemPerBlock;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {

@@ -63,6 +63,8 @@ class Opts(C.Structure):
 
 KERNEL_REGROUPED, KERNEL_PLAIN = 0, 1
 TABLES_AUTO, TABLES_LDS, TABLES_GLOBAL = 0, 1, 2          # mcd_opts.table_placement
+# mcd_measure_valu kinds
+VALU_FMA_F32, VALU_ADD_F32, VALU_MUL_F32, VALU_XAD_U32, VALU_MAD_U64, VALU_FMAMK_F32 = range(6)
 
 
 class Result(C.Structure):
@@ -141,6 +143,7 @@ def lib():
         L.mcd_check_philox.argtypes = [vp, C.c_uint32, C.c_uint32, vp, C.c_uint64, vp, vp]
         pi32 = C.POINTER(C.c_int32)
         L.mcd_launch_shape.argtypes = [vp, i32, C.POINTER(Opts), pi32, pi32, pi32, pi32, pi32]
+        L.mcd_measure_valu.argtypes = [vp, i32, i32, vp, C.POINTER(C.c_double), vp]
         L.mcd_check_tables.argtypes = [vp, i32, i32, i32, vp, C.c_uint64, vp, vp]
         L.mcd_status_string.argtypes = [C.c_int]
         L.mcd_status_string.restype = C.c_char_p
@@ -153,8 +156,8 @@ def lib():
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_load_materials", "mcd_unload_materials",
             "mcd_load_phantom", "mcd_unload_phantom", "mcd_simulate", "mcd_simulate_noalloc", "mcd_simulate_batch",
             "mcd_serve_configure", "mcd_submit", "mcd_submit_adaptive", "mcd_poll", "mcd_wait", "mcd_cancel",
-            "mcd_serve_stats_get", "mcd_check_philox", "mcd_check_tables", "mcd_measure_atomics", "mcd_launch_shape",
-            "mcd_status_string", "mcd_last_error")
+            "mcd_serve_stats_get", "mcd_check_philox", "mcd_check_tables", "mcd_measure_atomics", "mcd_measure_valu",
+            "mcd_launch_shape", "mcd_status_string", "mcd_last_error")
 
 # Quantities of mcd_check_tables (include/mcdose.h).
 Q_MU_C, Q_MU_PE, Q_MU_PP, Q_RANGE, Q_LAMBDA1_INV, Q_SIGMA_M, Q_SIGMA_B = range(7)
@@ -376,6 +379,16 @@ class Engine:
                     "mcd_launch_shape")
         return dict(zip(("grid_blocks", "block_size", "cu_count", "resident_per_cu", "table_placement"),
                         (x.value for x in v)))
+
+    def measure_valu(self, kind: int, iters: int = 200, stream=None) -> float:
+        """mcd_measure_valu: SIMD cycles per wave-wide operation of one VALU
+        instruction kind (VALU_* constants) at the peak engine clock."""
+        import torch
+        sink = torch.zeros(1, dtype=torch.float32, device=f"cuda:{self.device}")
+        cyc = C.c_double()
+        self._check(lib().mcd_measure_valu(self._h, kind, iters, sink.data_ptr(), C.byref(cyc),
+                                           _stream_ptr(stream)), "mcd_measure_valu")
+        return cyc.value
 
     def measure_atomics(self, target, idx, reps: int = 1, stream=None) -> float:
         """Device milliseconds for reps x idx.numel() FP64 atomic adds at
