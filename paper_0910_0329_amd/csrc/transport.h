@@ -28,6 +28,9 @@ namespace mcd {
 constexpr float kMC2 = 0.51099895f;
 constexpr float kLn2 = 0.693147180559945309f;
 constexpr float kInf = __builtin_huge_valf();
+// Draw-index flag of a secondary whose lineage is not computed yet (the
+// index bits then hold its parent's spawn index).
+constexpr uint32_t kLineagePending = 1u << 29;
 
 enum { PHOTON = 0, ELECTRON = 1, POSITRON = 2, DEAD = -1 };
 enum { LIM_E, LIM_H, LIM_K, LIM_B, LIM_F };
@@ -243,13 +246,28 @@ struct Transport {
         return ((float)(x >> 9) + 0.5f) * 0x1p-23f;
     }
 
-    DEV void child_lineage(Part& q, uint32_t& o0, uint32_t& o1)
+    // A secondary's lineage is the Philox block (h, parent lineage, 2^31 |
+    // spawn index) under the request key.  The parent only records its own
+    // lineage and the index in the secondary (d = kLineagePending | index);
+    // the block is computed when the secondary starts (start_particle), in a
+    // fetch with the other starting lanes rather than in the parent's
+    // interaction with the few lanes that spawn there.
+    DEV void defer_lineage(Part& q, Part& s)
     {
-        uint32_t c0 = q.h, c1 = q.l0, c2 = q.l1, c3 = 0x80000000u | q.nsp;
-        philox10(env.seed, env.key, c0, c1, c2, c3);
-        o0 = c0;
-        o1 = c1;
+        s.l0 = q.l0;
+        s.l1 = q.l1;
+        s.d = kLineagePending | q.nsp;
         ++q.nsp;
+    }
+
+    DEV void resolve_lineage(Part& q)
+    {
+        uint32_t c0 = q.h, c1 = q.l0, c2 = q.l1, c3 = 0x80000000u | (q.d & ~kLineagePending);
+        philox10(env.seed, env.key, c0, c1, c2, c3);
+        q.l0 = c0;
+        q.l1 = c1;
+        q.d = 0;
+        q.g = 0;
         count(MCD_C_PHILOX);
     }
 
@@ -366,8 +384,7 @@ struct Transport {
         s.u = u; s.v = v; s.w = w;
         s.h = q.h;
         s.slot = q.slot;
-        s.d = 0;
-        child_lineage(q, s.l0, s.l1);
+        defer_lineage(q, s);
         count(MCD_C_SPAWNS);
         self().spawn(s);
     }
@@ -398,8 +415,7 @@ struct Transport {
         s.u = u; s.v = v; s.w = w;
         s.h = q.h;
         s.slot = q.slot;
-        s.d = 0;
-        child_lineage(q, s.l0, s.l1);
+        defer_lineage(q, s);
         count(MCD_C_SPAWNS);
         self().spawn(s);
     }
@@ -495,6 +511,7 @@ struct Transport {
     DEV void start_particle(Part& q)
     {
         q.pend = 0;
+        if (q.d & kLineagePending) resolve_lineage(q);
         if (DIAG) p_hash = (0xcbf29ce484222325ull ^ ((uint64_t)q.l1 << 32 | q.l0)) * 0x100000001b3ull;
         if (q.type != PHOTON) {
             floor_voxel(q.x, q.y, q.z, q.ix, q.iy, q.iz);
