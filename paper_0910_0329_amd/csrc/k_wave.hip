@@ -33,8 +33,9 @@ enum { WS_PHOTON = 0, WS_ELECTRON = 1 };
 //   f0 = (x, y, z, E), f1 = (u, v, w, bits(type | slot << 4 | nsp << 16)),
 //   f2 = bits(l0, l1, h, d | ring << 31 | parked << 30), f3 = words of random
 // block d >> 2 (a parked photon that had drawn from it; ring = 1).  A fresh
-// secondary has d = 0 and nsp = 0 (its spawn count is not set yet) and leaves
-// f3 unwritten.  A parked particle also keeps its open tally visit (the voxel
+// secondary holds its parent's lineage, d = kLineagePending | spawn index and
+// nsp = 0 (its own spawn count starts at start_particle), and leaves f3
+// unwritten.  A parked particle also keeps its open tally visit (the voxel
 // and the FP32 sum of its deposits there so far), so that its deposits are
 // grouped as if it had never stopped: f4 = (bits(cur_v), cur_e, flags, 0), and
 // an electron f5 = bits(ix, iy, iz, 0), f6 = (nh, xi, kap, 0), flags = before

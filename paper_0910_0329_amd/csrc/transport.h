@@ -117,6 +117,8 @@ struct Part {
 
 // Particle record in a stack or queue: 48 bytes.
 //   f0 = (x, y, z, E), f1 = (u, v, w, bits(type | slot << 4)), f2 = bits(l0, l1, h, d)
+// A secondary not started yet holds its parent's lineage and
+// d = kLineagePending | spawn index (start_particle resolves it).
 DEV void store_rec(char* base, const Part& q)
 {
     float4* r = (float4*)base;
