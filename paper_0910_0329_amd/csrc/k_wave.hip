@@ -233,7 +233,14 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
         const uint64_t m = __builtin_amdgcn_ballot_w64(true);
         const unsigned rank =
             __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        const unsigned top0 = cnt[k];
+        // the first active lane reserves the slots with one LDS atomic (an
+        // LDS access, so only the LDS counter is waited for)
+        const unsigned n_push = (unsigned)__popcll(m);
+        unsigned base = 0u;
+        if (rank == 0)
+            base = __hip_atomic_fetch_add((__attribute__((address_space(3))) unsigned int*)(cnt + k), n_push,
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const unsigned top0 = __builtin_amdgcn_readfirstlane(base);
         const unsigned i = top0 + rank;
         if (i < cap()) {
             store_wave_rec(rec(k, i), s, parked);
@@ -242,8 +249,8 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
         } else {
             fail(MCD_E_OVERFLOW);
         }
-        const unsigned top = min(top0 + (unsigned)__popcll(m), cap());
-        cnt[k] = top;
+        const unsigned top = min(top0 + n_push, cap());
+        if (top0 + n_push > cap()) cnt[k] = top;      // overflow (failed above): keep the count in range
         if (DIAG && top > this->c[MCD_C_MAX_STACK]) this->c[MCD_C_MAX_STACK] = top;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     }
