@@ -257,6 +257,14 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
 
     DEV void spawn(const Part& s) { push(s.type == PHOTON ? WS_PHOTON : WS_ELECTRON, s, false, 0ull); }
 
+    // Sets the count of stack k with an LDS store (no wait for the wave's
+    // outstanding global stores).
+    DEV void lds_set_count(int k, unsigned v)
+    {
+        __hip_atomic_store((__attribute__((address_space(3))) unsigned int*)(cnt + k), v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+
     // Takes record i of stack k into q and starts it (a parked particle
     // resumes where it stopped, with its event hash; a fresh one starts anew).
     DEV bool take(int k, unsigned i, Part& q)
@@ -330,8 +338,8 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
         const int ka = prefer_photons ? WS_PHOTON : WS_ELECTRON, kb = 1 - ka;
         const unsigned ca = prefer_photons ? sg : se, cb = prefer_photons ? se : sg;
         const unsigned ta = min(nfl, ca), tb = can_claim ? 0u : min(nfl - ta, cb);
-        cnt[ka] = ca - ta;
-        cnt[kb] = cb - tb;
+        lds_set_count(ka, ca - ta);
+        lds_set_count(kb, cb - tb);
         // one take for both stacks (lanes of a fetch may take from either)
         if (rank < ta + tb) {
             const bool a = rank < ta;
@@ -373,7 +381,7 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
                 park(q);
                 take(to, top - 1 - rank, q);
             }
-            cnt[to] = top - k;
+            lds_set_count(to, top - k);
         }
     }
 
