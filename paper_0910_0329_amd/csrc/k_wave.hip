@@ -279,6 +279,7 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
         use_request(q.slot);
         if (parked) {
             load_parked_state(rec(k, i), q, cur_v, cur_e, k == WS_ELECTRON);
+            if (k == WS_ELECTRON) this->enter_voxel(q);
             if (DIAG) this->p_hash = hashes(k)[i];
         } else {
             this->start_particle(q);

@@ -110,6 +110,7 @@ struct Part {
     uint32_t nsp;            // secondaries spawned from this stream
     uint32_t r0, r1, r2, r3, r4, r5, r6, r7;  // ring: block k in words 4(k&1)..4(k&1)+3
     int ix, iy, iz;          // electron voxel (state, advanced across faces)
+    uint32_t vrho, vmat;     // that voxel's density bits and material (enter_voxel)
     float nh, xi, kap;       // hard-event mfps to go, hinge fraction, hinge budget
     int before;              // 1 before the hinge of the current step
     int pend;                // 1: the segment ended at a hard event not yet sampled
@@ -361,6 +362,15 @@ struct Transport {
 
     DEV int lin(int ix, int iy, int iz) const { return (iz * G().ny + iy) * G().nx + ix; }
 
+    // Loads the density and material of a charged particle's voxel once per
+    // voxel (its segments and hard events read them from the particle).
+    DEV void enter_voxel(Part& q) const
+    {
+        const uint2 vd = G().vox[lin(q.ix, q.iy, q.iz)];
+        q.vrho = vd.x;
+        q.vmat = vd.y;
+    }
+
     DEV void local(const Part& q, int v, float e)
     {
         count(MCD_C_LOCAL);
@@ -517,6 +527,7 @@ struct Transport {
         if (DIAG) p_hash = (0xcbf29ce484222325ull ^ ((uint64_t)q.l1 << 32 | q.l0)) * 0x100000001b3ull;
         if (q.type != PHOTON) {
             floor_voxel(q.x, q.y, q.z, q.ix, q.iy, q.iz);
+            enter_voxel(q);
             prefetch(q);                       // leaves >= 2 words
             q.nh = neg_ln(uni_ready(q));
             q.xi = uni_ready(q);
@@ -756,10 +767,9 @@ struct Transport {
         prefetch(q);
         const KGeom& g = G();
         const int vx = lin(q.ix, q.iy, q.iz);
-        const uint2 vd = g.vox[vx];
-        const float rho = __uint_as_float(vd.x);
+        const float rho = __uint_as_float(q.vrho);
         const float irho = __builtin_amdgcn_rcpf(rho);
-        const int m = (int)vd.y;
+        const int m = (int)q.vmat;
         const float T = q.e;
         const float xt = epos(T);
         int i;
@@ -862,6 +872,7 @@ struct Transport {
             q.iz += axis == 2 ? st : 0;
             const bool out = (unsigned)q.ix >= (unsigned)g.nx || (unsigned)q.iy >= (unsigned)g.ny ||
                              (unsigned)q.iz >= (unsigned)g.nz;
+            if (!out) enter_voxel(q);
             if (out) {
                 ev(EV_E_ESCAPE);
                 e_esc += (double)q.e + (q.type == POSITRON ? 2.0 * (double)kMC2 : 0.0);
@@ -930,7 +941,7 @@ struct Transport {
         q.pend = 0;
         prefetch(q, 4u);                       // the choice, a Moller try and its azimuth
         const int vx = lin(q.ix, q.iy, q.iz);
-        const int m = (int)g.vox[vx].y;
+        const int m = (int)q.vmat;
         float T = q.e;
         int i;
         float fr;
