@@ -63,8 +63,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # its reading for a 1 GiB device copy (profiles/transport_g6mv_hbm_traffic.md,
 # profiles/transport_e20_wlw_hbm_traffic.md).
 TRAFFIC_BYTES_PER_HIST = {
-    "g6mv_wbw_61x61x60": (17264457.0 * 2.0 + 46355729.28 * 1.0) * 1024 / 164442762,    # 503.7
-    "e20_wlw_32x32x30": (766627.25 * 2.0 + 16112660.44 * 1.0) * 1024 / 10_000_000,     # 1806.9
+    "g6mv_wbw_61x61x60": (17627115.25 * 2.0 + 46232087.78 * 1.0) * 1024 / 164442762,   # 507.4
+    "e20_wlw_32x32x30": (767015.5 * 2.0 + 16097100.0 * 1.0) * 1024 / 10_000_000,       # 1805.4
 }
 METRIC = "histories/s (6 MV photon, 20 MeV e-) at 1% sigma; p50/p99 dose-request latency"
 # The paper's Table 1 (Tesla C1060, FP32; DPM physics and a measured 6 MV
