@@ -317,12 +317,13 @@ def main():
     # the kinds the transport is made of (4 = 16 lanes per cycle, the rate the
     # peak assumes; an FMA issues faster, which the 157.3 TFLOP/s FP32 figure
     # counts)
-    from paper_0910_0329_amd.mcdose import (VALU_ADD_F32, VALU_FMA_F32, VALU_FMAMK_F32, VALU_MAD_U64,
-                                            VALU_MUL_F32, VALU_XAD_U32)
+    from paper_0910_0329_amd.mcdose import (VALU_ADD_F32, VALU_EXP_F32, VALU_FMA_F32, VALU_FMAMK_F32,
+                                            VALU_MAD_U64, VALU_MUL_F32, VALU_RCP_F32, VALU_XAD_U32)
     roofline["valu_issue_cycles"] = {
         name: eng.measure_valu(kind, 200) for name, kind in
         (("fma_f32", VALU_FMA_F32), ("fmamk_f32", VALU_FMAMK_F32), ("add_f32", VALU_ADD_F32),
-         ("mul_f32", VALU_MUL_F32), ("xad_u32", VALU_XAD_U32), ("mad_u64_plus_xor", VALU_MAD_U64))}
+         ("mul_f32", VALU_MUL_F32), ("xad_u32", VALU_XAD_U32), ("mad_u64_plus_xor", VALU_MAD_U64),
+         ("rcp_f32", VALU_RCP_F32), ("exp_f32", VALU_EXP_F32))}
     log(f"VALU issue cycles per wave64 operation: {roofline['valu_issue_cycles']}")
     line["roofline"] = roofline
 

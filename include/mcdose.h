@@ -292,8 +292,10 @@ int mcd_simulate(mcd_ctx* ctx, int32_t phantom, const mcd_source* src, uint64_t 
  * out->dose and out->sigma must be device buffers (out->on_device = 1); S is
  * optional and Q is refused.  opts as for mcd_simulate, except that kernel
  * must be MCD_KERNEL_REGROUPED, regroup 0 or 2, use_graph and accumulate 0.
- * The histories and results equal mcd_simulate's with the same arguments, up
- * to FP64 summation order.  Calls on one device share the array: the library
+ * The histories and results equal mcd_simulate's with the same arguments and
+ * regroup 2 (its lane-stack run), up to FP64 summation order; its default
+ * wave-stack run follows the same histories, with deposits that can differ in
+ * the last bits.  Calls on one device share the array: the library
  * runs them one at a time (calls that overlap from several threads or
  * contexts wait for each other). */
 int mcd_simulate_noalloc(mcd_ctx* ctx, int32_t phantom, const mcd_source* src, uint64_t n_histories,
@@ -490,12 +492,14 @@ int mcd_measure_atomics(mcd_ctx* ctx, double* target, uint64_t n_target, const u
  *   MCD_VALU_XAD_U32  one 32-bit xor-add (v_xad_u32)
  *   MCD_VALU_MAD_U64  a 32 x 32 -> 64-bit multiply (v_mad_u64_u32) and an xor,
  *                     the Philox round's product
- *   MCD_VALU_FMAMK_F32 one FMA with literal constants (v_fmamk_f32).
+ *   MCD_VALU_FMAMK_F32 one FMA with literal constants (v_fmamk_f32)
+ *   MCD_VALU_RCP_F32  one reciprocal (v_rcp_f32), a transcendental-unit op
+ *   MCD_VALU_EXP_F32  one base-2 exponential (v_exp_f32), likewise.
  * A wave64 instruction on a 16-lane SIMD takes 4 cycles; fewer means the
  * hardware issues it on wider datapaths.  sink: one device float the kernel
  * never writes in practice.  For the transport's ALU roofline. */
 enum { MCD_VALU_FMA_F32 = 0, MCD_VALU_ADD_F32 = 1, MCD_VALU_MUL_F32 = 2, MCD_VALU_XAD_U32 = 3,
-       MCD_VALU_MAD_U64 = 4, MCD_VALU_FMAMK_F32 = 5 };
+       MCD_VALU_MAD_U64 = 4, MCD_VALU_FMAMK_F32 = 5, MCD_VALU_RCP_F32 = 6, MCD_VALU_EXP_F32 = 7 };
 int mcd_measure_valu(mcd_ctx* ctx, int32_t kind, int32_t iters, float* sink, double* cycles_per_op,
                      void* hip_stream);
 

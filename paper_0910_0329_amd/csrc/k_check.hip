@@ -117,6 +117,10 @@ __global__ __launch_bounds__(256) void k_valu_rate(float x, uint32_t y, int iter
                     f[c] = f[c] + x;
                 } else if (KIND == MCD_VALU_MUL_F32) {
                     f[c] = f[c] * x;
+                } else if (KIND == MCD_VALU_RCP_F32) {
+                    f[c] = __builtin_amdgcn_rcpf(f[c]);
+                } else if (KIND == MCD_VALU_EXP_F32) {
+                    f[c] = __builtin_amdgcn_exp2f(f[c]);
                 } else if (KIND == MCD_VALU_XAD_U32) {
                     u[c] = (u[c] ^ (y + (uint32_t)r)) + (uint32_t)c;
                 } else {
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(256) void k_valu_rate(float x, uint32_t y, int iter
         us ^= u[c];
     }
     const bool fp = KIND == MCD_VALU_FMA_F32 || KIND == MCD_VALU_ADD_F32 || KIND == MCD_VALU_MUL_F32 ||
-                    KIND == MCD_VALU_FMAMK_F32;
+                    KIND == MCD_VALU_FMAMK_F32 || KIND == MCD_VALU_RCP_F32 || KIND == MCD_VALU_EXP_F32;
     if (fp ? fs == -12345.f : us == y + 0x9E3779B9u) sink[0] = fs + (float)us;
 }
 
@@ -227,7 +231,7 @@ int mcd_measure_valu(mcd_ctx* c, int32_t kind, int32_t iters, float* sink, doubl
                      void* hip_stream)
 {
     if (!c) return MCD_E_INVAL;
-    if (!sink || !cycles_per_op || kind < MCD_VALU_FMA_F32 || kind > MCD_VALU_FMAMK_F32 || iters < 1 ||
+    if (!sink || !cycles_per_op || kind < MCD_VALU_FMA_F32 || kind > MCD_VALU_EXP_F32 || iters < 1 ||
         iters > 100000)
         return c->fail(MCD_E_INVAL, "measure_valu: need a device sink, a known kind, 1 <= iters <= 1e5");
     mcd::DeviceGuard dg(c->device);
@@ -240,6 +244,8 @@ int mcd_measure_valu(mcd_ctx* c, int32_t kind, int32_t iters, float* sink, doubl
         : kind == MCD_VALU_MUL_F32 ? k_valu_rate<MCD_VALU_MUL_F32>
         : kind == MCD_VALU_XAD_U32 ? k_valu_rate<MCD_VALU_XAD_U32>
         : kind == MCD_VALU_MAD_U64 ? k_valu_rate<MCD_VALU_MAD_U64>
+        : kind == MCD_VALU_RCP_F32 ? k_valu_rate<MCD_VALU_RCP_F32>
+        : kind == MCD_VALU_EXP_F32 ? k_valu_rate<MCD_VALU_EXP_F32>
                                    : k_valu_rate<MCD_VALU_FMAMK_F32>;
     hipError_t e = hipEventRecord(c->ev[0], s);
     if (e == hipSuccess) {

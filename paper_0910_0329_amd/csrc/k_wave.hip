@@ -17,7 +17,9 @@
 //
 // A particle's stream and tally depend only on its own lineage and history
 // index, so which lane carries a particle, and when, does not change any
-// result: the histories are those of every other kernel.  The stack counts
+// result: the histories are those of every other kernel (their deposits can
+// differ in the last bits where the compiler fuses multiply-adds differently
+// in the two kernels' code).  The stack counts
 // live in LDS (one pair per wave, touched only by that wave), the records in
 // global memory; the wave's own instruction stream orders every push before
 // the pops that follow it.
@@ -455,7 +457,7 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
                 if (act == ST_FETCH) {
                     exhausted = !fetch_wave(q, mode == ST_PHOTON, can_claim, sgn, sen);
                 } else if (act == ST_PHOTON) {
-                    this->photon_step(q);
+                    this->template photon_step<2>(q);
                 } else if (act == ST_ELECTRON) {
                     this->electron_step(q);
                 } else {

@@ -605,44 +605,69 @@ struct Transport {
         q.type = s.particle;
     }
 
-    // One Woodcock flight and, if the stop is real, its interaction.
+    // Woodcock flights and, once a stop is real, its interaction.  Up to
+    // FLIGHTS flights per step: a flight that ends in a virtual event is
+    // followed by the next in the same step, so that the interaction runs
+    // with more of the wave's lanes while the lanes whose stop was real wait
+    // through the extra flight.  The wave-stack kernel takes two (a third
+    // costs more than it brings); the kernels that hold a particle per lane
+    // take one, which keeps their registers below the spill limit.  The
+    // particle's draws and events do not depend on FLIGHTS.
+    template <int FLIGHTS = 1>
     DEV void photon_step(Part& q)
     {
-        prefetch(q);
-        int i;
-        float fr;
-        eidx(q.e, i, fr);
-        const float mu_max = lerp(env.maj[i], env.maj[i + 1], fr);
-        const float s = fdiv(neg_ln(uni_ready(q)), mu_max);   // prefetch left >= 2 words
-        count(MCD_C_FLIGHTS);
-        q.x += s * q.u;
-        q.y += s * q.v;
-        q.z += s * q.w;
-        if (!inside(q.x, q.y, q.z)) {
-            ev(EV_G_ESCAPE);
-            e_esc += (double)q.e;
-            count(MCD_C_ESCAPES);
-            self().escaped(q);
-            end_particle(q);
-            return;
+        int i, vx, m;
+        float fr, mu_max, mu_c, s_pe, s_pp, s_r, xs;
+        for (int t = 0;; ++t) {
+            prefetch(q);
+            eidx(q.e, i, fr);
+            mu_max = lerp(env.maj[i], env.maj[i + 1], fr);
+            const float s = fdiv(neg_ln(uni_ready(q)), mu_max);   // prefetch left >= 2 words
+            count(MCD_C_FLIGHTS);
+            q.x += s * q.u;
+            q.y += s * q.v;
+            q.z += s * q.w;
+            if (!inside(q.x, q.y, q.z)) {
+                ev(EV_G_ESCAPE);
+                e_esc += (double)q.e;
+                count(MCD_C_ESCAPES);
+                self().escaped(q);
+                end_particle(q);
+                return;
+            }
+            int ix, iy, iz;
+            floor_voxel(q.x, q.y, q.z, ix, iy, iz);
+            vx = lin(ix, iy, iz);
+            const uint2 vd = G().vox[vx];
+            const float rho = __uint_as_float(vd.x);
+            m = (int)vd.y;
+            const float4 a = env.phot[m * kNE + i], b = env.phot[m * kNE + i + 1];
+            mu_c = rho * lerp(a.x, b.x, fr);
+            const float mu_pe = rho * lerp(a.y, b.y, fr);
+            const float mu_pp = rho * lerp(a.z, b.z, fr);
+            const float mu_r = REF ? rho * lerp(a.w, b.w, fr) : 0.f;
+            {
+                // running sums of the coefficients, each rounded on its own
+                // (no multiply-add contraction), so that the interaction
+                // tests below and the virtual test compare against the same
+                // values in every kernel that inlines this step
+#pragma clang fp contract(off)
+                s_pe = mu_c + mu_pe;
+                s_pp = s_pe + mu_pp;
+                s_r = s_pp + mu_r;
+            }
+            xs = uni_ready(q) * mu_max;
+            // virtual exactly when xs reaches the last sum (each earlier sum
+            // is at most it)
+            if (xs < (REF ? s_r : s_pp) || t == FLIGHTS - 1) break;
+            ev(EV_VIRTUAL);
+            count(MCD_C_VIRTUAL);
         }
-        int ix, iy, iz;
-        floor_voxel(q.x, q.y, q.z, ix, iy, iz);
-        const int vx = lin(ix, iy, iz);
-        const uint2 vd = G().vox[vx];
-        const float rho = __uint_as_float(vd.x);
-        const int m = (int)vd.y;
-        const float4 a = env.phot[m * kNE + i], b = env.phot[m * kNE + i + 1];
-        const float mu_c = rho * lerp(a.x, b.x, fr);
-        const float mu_pe = rho * lerp(a.y, b.y, fr);
-        const float mu_pp = rho * lerp(a.z, b.z, fr);
-        const float mu_r = REF ? rho * lerp(a.w, b.w, fr) : 0.f;
-        const float xs = uni_ready(q) * mu_max;
         if (xs < mu_c) {
             ev(EV_COMPTON);
             count(MCD_C_COMPTON);
             compton(q, vx);
-        } else if (xs < mu_c + mu_pe) {
+        } else if (xs < s_pe) {
             ev(EV_PHOTO);
             count(MCD_C_PHOTO);
             // the photoelectron leaves along the photon, or (angular tables,
@@ -655,7 +680,7 @@ struct Transport {
             }
             emit_charged(q, ELECTRON, q.e, q.x, q.y, q.z, du, dv, dw, vx);
             end_particle(q);
-        } else if (xs < mu_c + mu_pe + mu_pp) {
+        } else if (xs < s_pp) {
             if (q.e > 2.f * kMC2) {
                 ev(EV_PAIR);
                 count(MCD_C_PAIR);
@@ -685,7 +710,7 @@ struct Transport {
                 ev(EV_PAIR_VOID);
                 count(MCD_C_VOID);
             }
-        } else if (REF && xs < mu_c + mu_pe + mu_pp + mu_r) {
+        } else if (REF && xs < s_r) {
             // coherent: same energy, new direction
             ev(EV_RAYLEIGH);
             count(MCD_C_RAYLEIGH);
@@ -742,23 +767,20 @@ struct Transport {
     DEV float boundary(const Part& q, int& axis) const
     {
         const KGeom& g = G();
-        float best = kInf;
-        axis = 0;
-        if (q.u != 0.f) {
-            const float f = g.x0 + (float)(q.u > 0.f ? q.ix + 1 : q.ix) * g.dx;
-            best = fmaxf(0.f, fdiv(f - q.x, q.u));
-        }
-        if (q.v != 0.f) {
-            const float f = g.y0 + (float)(q.v > 0.f ? q.iy + 1 : q.iy) * g.dy;
-            const float dd = fmaxf(0.f, fdiv(f - q.y, q.v));
-            if (dd < best) { best = dd; axis = 1; }
-        }
-        if (q.w != 0.f) {
-            const float f = g.z0 + (float)(q.w > 0.f ? q.iz + 1 : q.iz) * g.dz;
-            const float dd = fmaxf(0.f, fdiv(f - q.z, q.w));
-            if (dd < best) { best = dd; axis = 2; }
-        }
-        return best;
+        // per axis with selects (lanes cross different faces); a direction
+        // component of zero never reaches its faces
+        const float fx = g.x0 + (float)(q.u > 0.f ? q.ix + 1 : q.ix) * g.dx;
+        const float fy = g.y0 + (float)(q.v > 0.f ? q.iy + 1 : q.iy) * g.dy;
+        const float fz = g.z0 + (float)(q.w > 0.f ? q.iz + 1 : q.iz) * g.dz;
+        const float bx = q.u != 0.f ? fmaxf(0.f, fdiv(fx - q.x, q.u)) : kInf;
+        const float by = q.v != 0.f ? fmaxf(0.f, fdiv(fy - q.y, q.v)) : kInf;
+        const float bz = q.w != 0.f ? fmaxf(0.f, fdiv(fz - q.z, q.w)) : kInf;
+        // ties go to the lower axis
+        const bool y_lt = by < bx;
+        const float bxy = y_lt ? by : bx;
+        const bool z_lt = bz < bxy;
+        axis = z_lt ? 2 : (y_lt ? 1 : 0);
+        return z_lt ? bz : bxy;
     }
 
     // One condensed-history segment inside the current voxel.

@@ -64,7 +64,8 @@ class Opts(C.Structure):
 KERNEL_REGROUPED, KERNEL_PLAIN = 0, 1
 TABLES_AUTO, TABLES_LDS, TABLES_GLOBAL = 0, 1, 2          # mcd_opts.table_placement
 # mcd_measure_valu kinds
-VALU_FMA_F32, VALU_ADD_F32, VALU_MUL_F32, VALU_XAD_U32, VALU_MAD_U64, VALU_FMAMK_F32 = range(6)
+(VALU_FMA_F32, VALU_ADD_F32, VALU_MUL_F32, VALU_XAD_U32, VALU_MAD_U64, VALU_FMAMK_F32, VALU_RCP_F32,
+ VALU_EXP_F32) = range(8)
 
 
 class Result(C.Structure):

@@ -224,15 +224,17 @@ def test_measure_valu_reports_issue_cycles(eng):
     """The issue-rate probe runs each instruction kind and reports a plausible
     cycle count per wave64 operation (a 16-lane SIMD needs 4 cycles for a
     wave64 instruction; a datapath twice as wide 2; the 64-bit multiply and
-    its xor are two instructions)."""
+    its xor are two instructions; the transcendental unit is not faster than
+    the FMA datapath)."""
     from paper_0910_0329_amd import mcdose
     got = {}
     for kind in (mcdose.VALU_FMA_F32, mcdose.VALU_ADD_F32, mcdose.VALU_MUL_F32, mcdose.VALU_XAD_U32,
-                 mcdose.VALU_MAD_U64, mcdose.VALU_FMAMK_F32):
+                 mcdose.VALU_MAD_U64, mcdose.VALU_FMAMK_F32, mcdose.VALU_RCP_F32, mcdose.VALU_EXP_F32):
         got[kind] = eng.measure_valu(kind, 50)
         log(f"  kind {kind}: {got[kind]:.2f} cycles per wave64 operation")
         assert 1.0 <= got[kind] <= 64.0
     assert got[mcdose.VALU_MAD_U64] > got[mcdose.VALU_XAD_U32]
+    assert got[mcdose.VALU_RCP_F32] >= 0.9 * got[mcdose.VALU_FMA_F32]
     with pytest.raises(RuntimeError):
         eng.measure_valu(9, 10)
 

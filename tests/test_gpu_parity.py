@@ -616,7 +616,11 @@ def test_top_of_the_history_range(eng, blob, th, kernel):
 
 def test_batch_equals_separate_runs(eng, th):
     """Several beams with uneven history counts in one regrouped launch give each
-    beam the result of its own run (same keys); repeated graph replays agree."""
+    beam the result of its own run with the same kernel (same keys); repeated
+    graph replays agree.  Each batch form is compared with separate runs of its
+    own kernel: different kernels follow the same histories (see
+    test_kernels_agree_on_histories) but may round a few deposits differently,
+    where the compiler fuses multiply-adds differently in their code."""
     ph = phantoms.water_bone_water_61()
     pid = eng.load_phantom(ph, th)
     x, y = ph.centre_xy()
@@ -635,11 +639,12 @@ def test_batch_equals_separate_runs(eng, th):
     esum = 0.0
     for (src, n, key), o, o2, o3 in zip(items, outs, outs2, outs3):
         alone = eng.simulate(pid, src, n, 4, key, n_vox=nv, want_tallies=True)
-        for r in (o, o2, o3):
-            np.testing.assert_allclose(r["S"].cpu().numpy(), alone["S"].cpu().numpy(), rtol=1e-9, atol=1e-12)
-            np.testing.assert_allclose(r["dose"].cpu().numpy(), alone["dose"].cpu().numpy(), rtol=1e-9, atol=1e-25)
-            np.testing.assert_allclose(r["sigma"].cpu().numpy(), alone["sigma"].cpu().numpy(), rtol=1e-6, atol=1e-25)
-            assert r["dmax"] == pytest.approx(alone["dmax"], rel=1e-9)
+        alone_q = eng.simulate(pid, src, n, 4, key, n_vox=nv, want_tallies=True, regroup=1)
+        for r, a in ((o, alone), (o2, alone_q), (o3, alone_q)):
+            np.testing.assert_allclose(r["S"].cpu().numpy(), a["S"].cpu().numpy(), rtol=1e-9, atol=1e-12)
+            np.testing.assert_allclose(r["dose"].cpu().numpy(), a["dose"].cpu().numpy(), rtol=1e-9, atol=1e-25)
+            np.testing.assert_allclose(r["sigma"].cpu().numpy(), a["sigma"].cpu().numpy(), rtol=1e-6, atol=1e-25)
+            assert r["dmax"] == pytest.approx(a["dmax"], rel=1e-9)
         esum += alone["bal"]["E_src"]
     assert tot["bal"]["E_src"] == pytest.approx(esum, rel=1e-9)
     eng.unload_phantom(pid)

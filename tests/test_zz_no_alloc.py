@@ -1,7 +1,8 @@
 """mcd_simulate_noalloc against mcd_simulate: the entry point for callers that
-cannot allocate runs the same regrouped transport with its buffers in the
-library's fixed device array, so its results must equal the allocating
-entry point's (same histories; FP64 atomics add in another order).  Two calls
+cannot allocate runs the regrouped lane-stack transport with its buffers in
+the library's fixed device array, so its results must equal the allocating
+entry point's run with that transport (regroup 2; same histories, FP64 atomics
+add in another order).  Two calls
 in a row, the second on a smaller phantom with fewer histories, so a stale
 tally or counter from the first would show; free device memory does not move
 across the calls; a run too large for the array is refused."""
@@ -54,7 +55,7 @@ def test_noalloc_equals_simulate_on_two_calls(eng, blob):
     assert torch.cuda.mem_get_info()[0] == free0
     for (w, p), (r, d, s, S) in zip(cases, got):
         ref = eng.simulate(p, w.source, w.n_histories, w.seed, w.request_key, n_vox=w.phantom.n_vox,
-                           want_tallies=True)
+                           want_tallies=True, regroup=2)
         np.testing.assert_allclose(S, ref["S"].cpu().numpy(), rtol=1e-9, atol=1e-12)
         np.testing.assert_allclose(d, ref["dose"].cpu().numpy(), rtol=1e-9, atol=1e-25)
         np.testing.assert_allclose(s, ref["sigma"].cpu().numpy(), rtol=1e-6, atol=1e-25)
