@@ -176,9 +176,9 @@ typedef struct {
      * least electrons/photon_div; else electron segments.  1..64, 0 = default:
      * plain kernel (3, 24, 2); regrouped kernel with lane stacks or queues
      * (3, 24, 2) when every source is a photon source, else (4, 8, 6); with
-     * wave stacks (regroup 0 or 3) (4, 24, 1) or (6, 8, 1), where photon_div
-     * instead sets the mode switch (the mode's work below 64 / photon_div
-     * lanes). */
+     * wave stacks (regroup 0 or 3) (16, 24, 1) or (16, 64, 1), where
+     * photon_div instead sets the mode switch (the mode's work below
+     * 64 / photon_div lanes) and fetch_div holds in electron mode only. */
     int32_t sched_fetch_div;
     int32_t sched_hard_div;
     int32_t sched_photon_div;
@@ -196,6 +196,10 @@ typedef struct {
                                  (large table sets), then device memory; the other
                                  schedules always use the LDS.  The histories are the same
                                  either way. */
+    int32_t sched_fetch_photon_div; /* wave stacks (regroup 0 or 3): the fetch threshold
+                                 while the wave is in photon mode (1/this of its live
+                                 lanes need a particle); 1..64, 0 = default 2.  Ignored
+                                 by the other schedules. */
 } mcd_opts;
 
 /* Output of a run.  dose and sigma (nx*ny*nz doubles each, Gy per source

@@ -28,12 +28,14 @@ DEFAULT_SPACE = {
     "block_size": (256, 512),
     "table_placement": (1, 2),          # MCD_TABLES_LDS, MCD_TABLES_GLOBAL
 }
-# second stage, searched around the best launch options (with wave stacks,
-# regroup 3, photon_div sets the photon/electron mode switch)
+# third stage, searched around the best launch options: the wave-stack
+# schedule's thresholds (regroup 3: fetch_div holds in electron mode,
+# fetch_photon_div in photon mode, photon_div sets the mode switch)
 SCHED_SPACE = {
-    "sched_fetch_div": (3, 4, 6),
-    "sched_hard_div": (8, 24),
-    "sched_photon_div": (1, 2, 6),
+    "sched_fetch_div": (8, 16),
+    "sched_fetch_photon_div": (2, 3),
+    "sched_hard_div": (24, 64),
+    "sched_photon_div": (1,),
 }
 CACHE_ENV = "MCDOSE_TUNE_CACHE"
 

@@ -56,6 +56,7 @@ struct Sched {
     int fetch_div;           // fetch when >= 1/fetch_div of the live lanes need a particle
     int hard_div;            // sample hard events when >= 1/hard_div of the live lanes wait
     int photon_div;          // photon flights when photons >= electrons / photon_div
+    int fetch_photon_div;    // wave stacks: fetch_div while the wave is in photon mode
 };
 
 // Tables and phantom of a launch.

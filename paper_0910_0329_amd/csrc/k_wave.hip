@@ -446,7 +446,8 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
             const bool fetchable = sg + se > 0 || can_claim;
             const int nfe = fetchable ? nf : 0;
             int act;
-            if (nfe && (nfe * sc.fetch_div >= n || nfe == n)) act = ST_FETCH;
+            const int fdiv = mode == ST_PHOTON ? sc.fetch_photon_div : sc.fetch_div;
+            if (nfe && (nfe * fdiv >= n || nfe == n)) act = ST_FETCH;
             else if (nh && (nh * sc.hard_div >= n || nh + nf == n)) act = ST_HARD;
             else if (mode == ST_PHOTON ? np : ne) act = mode;
             else if (np) act = ST_PHOTON;

@@ -33,17 +33,21 @@ constexpr int kMaxBatch = 4096;
 // sources fetch at 1/4, sample hard events at 1/8 and fly photons at a sixth
 // of the electrons.  The plain kernel does best at (3, 24, 2) for both.
 struct SchedDefaults {
-    int fetch_div, hard_div, photon_div;
+    int fetch_div, hard_div, photon_div, fetch_photon_div;
 };
-constexpr SchedDefaults kSchedPhotonSources{3, 24, 2};
-constexpr SchedDefaults kSchedChargedSources{4, 8, 6};
-constexpr SchedDefaults kSchedPlain{3, 24, 2};
-// Wave-stack schedule (the default regrouped one): fetch at 1/4 (photon
-// sources) or 1/6 of the lanes, hard events at 1/24 or 1/8; photon_div there
-// sets when the wave leaves its photon or electron mode (work of the mode's
-// kind below 64 / photon_div lanes): 1, as soon as it cannot fill the wave.
-constexpr SchedDefaults kSchedWavePhotonSources{4, 24, 1};
-constexpr SchedDefaults kSchedWaveChargedSources{6, 8, 1};
+constexpr SchedDefaults kSchedPhotonSources{3, 24, 2, 3};
+constexpr SchedDefaults kSchedChargedSources{4, 8, 6, 4};
+constexpr SchedDefaults kSchedPlain{3, 24, 2, 3};
+// Wave-stack schedule (the default regrouped one).  In electron mode a wave
+// fetches once 1/16 of its lanes are idle (an electron step runs many
+// segments, so idle lanes are expensive there); in photon mode once half of
+// them are (fuller fetch steps between short photon steps).  Hard events at
+// 1/24 of the lanes for photon sources and as soon as one lane waits for
+// charged sources.  photon_div there sets when the wave leaves its photon or
+// electron mode (work of the mode's kind below 64 / photon_div lanes): 1, as
+// soon as it cannot fill the wave.
+constexpr SchedDefaults kSchedWavePhotonSources{16, 24, 1, 2};
+constexpr SchedDefaults kSchedWaveChargedSources{16, 64, 1, 2};
 
 // Small per-run device block: energy balance, counters, error flag, work
 // counter and finalisation reductions of the plain kernel.
