@@ -312,7 +312,7 @@ static void run_epoch(mcd_ctx* c, mcd_server* S)
         // four cycles' worth: each epoch ends with a tail in which few waves
         // are busy, so short epochs pay more tails, and long ones hold small
         // requests back (on the 20 req/s mixed stream half this size raised
-        // p99 by 16%, twice this size p50 by 24%)
+        // p50 by 8% and p99 by 10%, twice this size p99 by 4%)
         budget = 4 * (uint64_t)blocks * threads * (uint64_t)cpl;
     }
     std::sort(batch.begin(), batch.end(),
