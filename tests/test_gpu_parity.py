@@ -614,6 +614,32 @@ def test_top_of_the_history_range(eng, blob, th, kernel):
     assert f > 0.98                   # measured 0.9988
 
 
+@pytest.mark.parametrize("particle", [PHOTON, ELECTRON])
+def test_wave_schedule_thresholds_do_not_change_results(eng, th, particle):
+    """The wave-stack schedule's thresholds (fetch in electron and in photon
+    mode, hard events, mode switch) only decide when a lane's steps run, never
+    what they compute: extreme settings give the default run's per-voxel sums
+    up to FP64 summation order.  Out-of-range thresholds are refused."""
+    from paper_0910_0329_amd.mcdose import E_INVAL, McdError
+    w = configs.photon_6mv_wbw(60_000) if particle == PHOTON else configs.electron_20mev_wlw(6_000)
+    pid = eng.load_phantom(w.phantom, th)
+    nv = w.phantom.n_vox
+    log(f"case schedule thresholds {w.name} n={w.n_histories}")
+    ref = eng.simulate(pid, w.source, w.n_histories, w.seed, n_vox=nv, want_tallies=True, regroup=3)
+    for sched in ({"sched_fetch_div": 1, "sched_fetch_photon_div": 64},
+                  {"sched_fetch_div": 64, "sched_fetch_photon_div": 1},
+                  {"sched_hard_div": 1, "sched_photon_div": 8},
+                  {"sched_hard_div": 64, "sched_photon_div": 64}):
+        r = eng.simulate(pid, w.source, w.n_histories, w.seed, n_vox=nv, want_tallies=True, regroup=3, **sched)
+        np.testing.assert_allclose(r["S"].cpu().numpy(), ref["S"].cpu().numpy(), rtol=1e-9, atol=1e-12)
+        assert r["bal"]["E_csda"] == pytest.approx(ref["bal"]["E_csda"], rel=1e-12)
+    for bad in ({"sched_fetch_photon_div": 65}, {"sched_fetch_photon_div": -1}, {"sched_fetch_div": 65}):
+        with pytest.raises(McdError) as ei:
+            eng.simulate(pid, w.source, 1000, w.seed, n_vox=nv, regroup=3, **bad)
+        assert ei.value.status == E_INVAL
+    eng.unload_phantom(pid)
+
+
 def test_batch_equals_separate_runs(eng, th):
     """Several beams with uneven history counts in one regrouped launch give each
     beam the result of its own run with the same kernel (same keys); repeated
