@@ -356,7 +356,7 @@ def main():
 
     # ------------------------------------------------------------ electrons
     electron = {"workload": we.name}
-    pe_pilot = run(we, pe, 1_000_000, kernel=KERNEL_PLAIN)
+    pe_pilot = run(we, pe, 1_000_000, kernel=KERNEL_PLAIN, want_tallies=True)
     n1e = max(2, int(math.ceil(1_000_000 * (pe_pilot["sigma_bar"] / 0.01) ** 2)))
     reps = 20
     te, re_ = timed(lambda: run(we, pe, n1e), reps)
@@ -377,6 +377,13 @@ def main():
         # one launch per step in lane-stack mode: bytes per launch, and HBM rate
         electron["pencil_1e7"]["traffic"] = pe_tb * we.n_histories / max(re_["launches"], 1)
         electron["pencil_1e7"]["hbm_frac"] = pe_tb * we.n_histories / (re_["kernel_ms"] * 1e-3) / 8e12
+    # the pencil beam's flushes crowd the beam axis: their rate against the
+    # device's rate on the same address pattern (drawn from the pilot's S^2/Q)
+    rde = run(we, pe, 200_000, diagnostics=1, want_dose=False)
+    e_flushes = rde["cnt"]["flushes"] / 200_000
+    electron["pencil_1e7"]["atomic"] = atomic_ceilings(
+        eng, we.phantom.n_vox, pe_pilot["S"].cpu().numpy(), pe_pilot["Q"].cpu().numpy(),
+        e_flushes * we.n_histories / (re_["kernel_ms"] * 1e-3), e_flushes)
     wf = configs.electron_20mev_point_field(we.phantom, 1_000_000)
     fpilot = run(wf, pe, wf.n_histories, kernel=KERNEL_PLAIN)
     n1f = int(math.ceil(wf.n_histories * (fpilot["sigma_bar"] / 0.01) ** 2))
