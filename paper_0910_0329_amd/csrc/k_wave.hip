@@ -467,14 +467,20 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
                     exhausted = !fetch_wave(q, mode == ST_PHOTON, can_claim, sgn, sen);
                 } else if (act == ST_PHOTON) {
                     this->template photon_step<2>(q);
-                } else if (act == ST_ELECTRON) {
-#pragma nounroll
-                    for (int t = 0;;) {
-                        this->electron_step(q);
-                        if (++t == kSegmentsPerStep || q.type == DEAD || q.pend) break;
-                    }
                 } else {
-                    this->hard_event(q);
+                    if (act == ST_ELECTRON) {
+#pragma nounroll
+                        for (int t = 0;;) {
+                            this->electron_step(q);
+                            if (++t == kSegmentsPerStep || q.type == DEAD || q.pend) break;
+                        }
+                    }
+                    // with photon sources, lanes whose electron step stopped at
+                    // a hard event sample it at once, without a schedule
+                    // decision in between (+0.3-1.2% on the photon workloads;
+                    // with electron sources waiting for the next decision,
+                    // which may fetch first, did 3-6% better)
+                    if (q.type != DEAD && q.pend && (act == ST_HARD || claim_photon)) this->hard_event(q);
                 }
             }
             if (__builtin_amdgcn_ballot_w64(exhausted) != 0) more_new = false;
