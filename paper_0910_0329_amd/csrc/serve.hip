@@ -484,6 +484,9 @@ static int check_config(mcd_ctx* c, const mcd_serve_config* cfg)
         return c->fail(MCD_E_INVAL, "serve config: epoch_histories < 2^40");
     if (cfg->phantom_order != MCD_PHANTOMS_SHORTEST && cfg->phantom_order != MCD_PHANTOMS_IN_TURN)
         return c->fail(MCD_E_INVAL, "serve config: phantom_order must be MCD_PHANTOMS_SHORTEST or _IN_TURN");
+    mcd::Sched sc;
+    int rc = c->wave_schedule(&o, &sc, mcd::kSchedWavePhotonSources);   // thresholds in range
+    if (rc) return rc;
     int b = 0, t = 0;
     return c->launch_shape(&o, 1, &b, &t);
 }

@@ -248,10 +248,13 @@ def test_memory_limit_admission(eng, pool, th):
 
 
 def test_phantom_order_is_validated(eng):
+    """An unknown phantom order, or wave-schedule thresholds out of range, are
+    refused when the loop is configured, not when an epoch runs."""
     from paper_0910_0329_amd.mcdose import E_INVAL, McdError
-    with pytest.raises(McdError) as ei:
-        eng.serve_configure(phantom_order=2)
-    assert ei.value.status == E_INVAL
+    for bad in ({"phantom_order": 2}, {"sched_fetch_photon_div": 65}, {"sched_hard_div": -3}):
+        with pytest.raises(McdError) as ei:
+            eng.serve_configure(**bad)
+        assert ei.value.status == E_INVAL
     eng.serve_configure()
 
 
