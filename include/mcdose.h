@@ -200,6 +200,11 @@ typedef struct {
                                  while the wave is in photon mode (1/this of its live
                                  lanes need a particle); 1..64, 0 = default 2.  Ignored
                                  by the other schedules. */
+    int32_t sched_segments;   /* wave stacks (regroup 0 or 3): condensed-history segments
+                                 an electron step may run before the wave's next schedule
+                                 decision (a lane stops early at a hard event or at its
+                                 particle's end); 1..64, 0 = default 12.  Ignored by the
+                                 other schedules.  The histories do not depend on it. */
 } mcd_opts;
 
 /* Output of a run.  dose and sigma (nx*ny*nz doubles each, Gy per source

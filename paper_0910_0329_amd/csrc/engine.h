@@ -57,6 +57,7 @@ struct Sched {
     int hard_div;            // sample hard events when >= 1/hard_div of the live lanes wait
     int photon_div;          // photon flights when photons >= electrons / photon_div
     int fetch_photon_div;    // wave stacks: fetch_div while the wave is in photon mode
+    int segments;            // wave stacks: segments an electron step may run
 };
 
 // Tables and phantom of a launch.

@@ -28,13 +28,13 @@
 namespace mcd {
 
 constexpr int kWaveRec = 80;         // bytes per photon-stack record
-// Condensed-history segments an electron step runs before the wave returns to
-// its schedule: a lane goes on with its next segment while its particle stays
-// a charged particle without a pending hard event (lanes that stop wait for
-// the others).  The schedule's bookkeeping at the loop top costs more than
-// the lanes that idle through the remaining segments; a fixed count did
-// better than stopping once half the lanes had stopped.
-constexpr int kSegmentsPerStep = 12;
+// An electron step runs up to Sched::segments condensed-history segments (12
+// by default) before the wave returns to its schedule: a lane goes on with its
+// next segment while its particle stays a charged particle without a pending
+// hard event (lanes that stop wait for the others).  The schedule's
+// bookkeeping at the loop top costs more than the lanes that idle through the
+// remaining segments; a fixed count did better than stopping once half the
+// lanes had stopped.
 constexpr int kWaveERec = 112;       // bytes per electron-stack record (with the electron state)
 enum { WS_PHOTON = 0, WS_ELECTRON = 1 };
 
@@ -368,8 +368,8 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
     // electron): lanes holding the other kind park and take waiting particles
     // of the mode's kind; fetching lanes count only while something can be
     // fetched; steps of the mode's kind run unless fetch or hard-event
-    // thresholds call (an electron step runs up to kSegmentsPerStep
-    // segments, a photon step up to two flights); the wave ends when no lane
+    // thresholds call (an electron step runs up to sc.segments segments, a
+    // photon step up to two flights); the wave ends when no lane
     // holds a particle and nothing is left to fetch.
     enum { ST_FETCH, ST_PHOTON, ST_ELECTRON, ST_HARD };
 
@@ -472,7 +472,7 @@ struct WaveLane : Transport<WaveLane<DIAG, REF>, DIAG, REF> {
 #pragma nounroll
                         for (int t = 0;;) {
                             this->electron_step(q);
-                            if (++t == kSegmentsPerStep || q.type == DEAD || q.pend) break;
+                            if (++t == sc.segments || q.type == DEAD || q.pend) break;
                         }
                     }
                     // with photon sources, lanes whose electron step stopped at

@@ -33,11 +33,11 @@ constexpr int kMaxBatch = 4096;
 // sources fetch at 1/4, sample hard events at 1/8 and fly photons at a sixth
 // of the electrons.  The plain kernel does best at (3, 24, 2) for both.
 struct SchedDefaults {
-    int fetch_div, hard_div, photon_div, fetch_photon_div;
+    int fetch_div, hard_div, photon_div, fetch_photon_div, segments;
 };
-constexpr SchedDefaults kSchedPhotonSources{3, 24, 2, 3};
-constexpr SchedDefaults kSchedChargedSources{4, 8, 6, 4};
-constexpr SchedDefaults kSchedPlain{3, 24, 2, 3};
+constexpr SchedDefaults kSchedPhotonSources{3, 24, 2, 3, 1};
+constexpr SchedDefaults kSchedChargedSources{4, 8, 6, 4, 1};
+constexpr SchedDefaults kSchedPlain{3, 24, 2, 3, 1};
 // Wave-stack schedule (the default regrouped one).  In electron mode a wave
 // fetches once 1/16 of its lanes are idle (an electron step runs many
 // segments, so idle lanes are expensive there); in photon mode once half of
@@ -45,9 +45,10 @@ constexpr SchedDefaults kSchedPlain{3, 24, 2, 3};
 // 1/24 of the lanes for photon sources and as soon as one lane waits for
 // charged sources.  photon_div there sets when the wave leaves its photon or
 // electron mode (work of the mode's kind below 64 / photon_div lanes): 1, as
-// soon as it cannot fill the wave.
-constexpr SchedDefaults kSchedWavePhotonSources{16, 24, 1, 2};
-constexpr SchedDefaults kSchedWaveChargedSources{16, 64, 1, 2};
+// soon as it cannot fill the wave.  An electron step runs up to 12 segments
+// before the wave decides again.
+constexpr SchedDefaults kSchedWavePhotonSources{16, 24, 1, 2, 12};
+constexpr SchedDefaults kSchedWaveChargedSources{16, 64, 1, 2, 12};
 
 // Small per-run device block: energy balance, counters, error flag, work
 // counter and finalisation reductions of the plain kernel.

@@ -86,10 +86,12 @@ int mcd_ctx::wave_schedule(const mcd_opts* o, Sched* sc, SchedDefaults d)
     sc->hard_div = o && o->sched_hard_div ? o->sched_hard_div : d.hard_div;
     sc->photon_div = o && o->sched_photon_div ? o->sched_photon_div : d.photon_div;
     sc->fetch_photon_div = o && o->sched_fetch_photon_div ? o->sched_fetch_photon_div : d.fetch_photon_div;
+    sc->segments = o && o->sched_segments ? o->sched_segments : d.segments;
     if (sc->fetch_div < 1 || sc->fetch_div > 64 || sc->hard_div < 1 || sc->hard_div > 64 ||
-        sc->photon_div < 1 || sc->photon_div > 64 || sc->fetch_photon_div < 1 || sc->fetch_photon_div > 64)
+        sc->photon_div < 1 || sc->photon_div > 64 || sc->fetch_photon_div < 1 || sc->fetch_photon_div > 64 ||
+        sc->segments < 1 || sc->segments > 64)
         return fail(MCD_E_INVAL, "opts: sched_fetch_div, sched_hard_div, sched_photon_div, "
-                                 "sched_fetch_photon_div in [0, 64]");
+                                 "sched_fetch_photon_div, sched_segments in [0, 64]");
     return MCD_OK;
 }
 

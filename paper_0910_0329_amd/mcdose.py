@@ -58,7 +58,8 @@ class Opts(C.Structure):
                 ("chunk_per_lane", C.c_int32), ("use_graph", C.c_int32), ("regroup", C.c_int32),
                 ("sched_fetch_div", C.c_int32), ("sched_hard_div", C.c_int32),
                 ("sched_photon_div", C.c_int32), ("refined_build", C.c_int32),
-                ("table_placement", C.c_int32), ("sched_fetch_photon_div", C.c_int32)]
+                ("table_placement", C.c_int32), ("sched_fetch_photon_div", C.c_int32),
+                ("sched_segments", C.c_int32)]
 
 
 KERNEL_REGROUPED, KERNEL_PLAIN = 0, 1

@@ -617,9 +617,10 @@ def test_top_of_the_history_range(eng, blob, th, kernel):
 @pytest.mark.parametrize("particle", [PHOTON, ELECTRON])
 def test_wave_schedule_thresholds_do_not_change_results(eng, th, particle):
     """The wave-stack schedule's thresholds (fetch in electron and in photon
-    mode, hard events, mode switch) only decide when a lane's steps run, never
-    what they compute: extreme settings give the default run's per-voxel sums
-    up to FP64 summation order.  Out-of-range thresholds are refused."""
+    mode, hard events, mode switch, segments per electron step) only decide
+    when a lane's steps run, never what they compute: extreme settings give
+    the default run's per-voxel sums up to FP64 summation order.  Out-of-range
+    thresholds are refused."""
     from paper_0910_0329_amd.mcdose import E_INVAL, McdError
     w = configs.photon_6mv_wbw(60_000) if particle == PHOTON else configs.electron_20mev_wlw(6_000)
     pid = eng.load_phantom(w.phantom, th)
@@ -629,11 +630,13 @@ def test_wave_schedule_thresholds_do_not_change_results(eng, th, particle):
     for sched in ({"sched_fetch_div": 1, "sched_fetch_photon_div": 64},
                   {"sched_fetch_div": 64, "sched_fetch_photon_div": 1},
                   {"sched_hard_div": 1, "sched_photon_div": 8},
-                  {"sched_hard_div": 64, "sched_photon_div": 64}):
+                  {"sched_hard_div": 64, "sched_photon_div": 64},
+                  {"sched_segments": 1}, {"sched_segments": 64}):
         r = eng.simulate(pid, w.source, w.n_histories, w.seed, n_vox=nv, want_tallies=True, regroup=3, **sched)
         np.testing.assert_allclose(r["S"].cpu().numpy(), ref["S"].cpu().numpy(), rtol=1e-9, atol=1e-12)
         assert r["bal"]["E_csda"] == pytest.approx(ref["bal"]["E_csda"], rel=1e-12)
-    for bad in ({"sched_fetch_photon_div": 65}, {"sched_fetch_photon_div": -1}, {"sched_fetch_div": 65}):
+    for bad in ({"sched_fetch_photon_div": 65}, {"sched_fetch_photon_div": -1}, {"sched_fetch_div": 65},
+                {"sched_segments": 65}):
         with pytest.raises(McdError) as ei:
             eng.simulate(pid, w.source, 1000, w.seed, n_vox=nv, regroup=3, **bad)
         assert ei.value.status == E_INVAL
