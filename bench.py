@@ -63,8 +63,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # its reading for a 1 GiB device copy (profiles/transport_g6mv_hbm_traffic.md,
 # profiles/transport_e20_wlw_hbm_traffic.md).
 TRAFFIC_BYTES_PER_HIST = {
-    "g6mv_wbw_61x61x60": (16073669.625 * 2.0 + 42855205.06 * 1.0) * 1024 / 164442762,  # 467.0
-    "e20_wlw_32x32x30": (1139772.1875 * 2.0 + 16270953.22 * 1.0) * 1024 / 10_000_000,  # 1899.6
+    "g6mv_wbw_61x61x60": (16080082.0 * 2.0 + 42854716.0 * 1.0) * 1024 / 164442762,     # 467.1
+    "e20_wlw_32x32x30": (1148667.8125 * 2.0 + 16281907.75 * 1.0) * 1024 / 10_000_000,  # 1902.5
 }
 METRIC = "histories/s (6 MV photon, 20 MeV e-) at 1% sigma; p50/p99 dose-request latency"
 # The paper's Table 1 (Tesla C1060, FP32; DPM physics and a measured 6 MV
